@@ -1,0 +1,490 @@
+// Unfolding GEMMs of the PASD iteration on gfx950 matrix cores.
+//
+//   GEMM-M : M_n = G_n P_n^T      (I_n x R_n, contraction over the J_n columns)
+//            whose orthonormal basis is the new active subspace U_n
+//            (Procrustes step, eqs. (9)-(10));
+//   GEMM-P : P_n = U_n^T G_n      (R_n x J_n, contraction over I_n),
+//            the matrix whose SVT is V_n (eq. (13));
+//   Gram   : S_n = P_n P_n^T      (R_n x R_n, FP64), for the SVT by eigensolver;
+//
+// with G_n = T_(n) - E_(n) + Y_n,(n) / mu formed on the fly from D = T - E and
+// Y_n (definition under eq. (9)); G is never stored.
+//
+// All three use v_mfma_{f32,f64}_16x16x4 with the rank padded to one 16-wide
+// tile.  The unfolding is read in place through its (A, I, B) geometry.  The
+// contraction index inside one MFMA is permuted freely (both operands use the
+// same permutation), which lets every lane issue 4-element vector loads along
+// the contiguous direction of the tensor.  Split-K partial sums are reduced
+// in LDS within a block and across blocks by a separate, fixed-order pass, so
+// results are bitwise reproducible.
+#include <algorithm>
+
+#include "pasd_internal.hpp"
+
+namespace pasd {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <typename S> struct MM;
+// Operand layout of both 16x16x4 instructions: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16].  Result element v of lane l is D[row(l / 16, v)][l % 16]
+// with row = 4 (l/16) + v for the f32 instruction and 4 v + l/16 for the f64
+// one (measured on gfx950).
+template <> struct MM<float> {
+  typedef f4v acc_t;
+  typedef f4v vec_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+};
+template <> struct MM<double> {
+  typedef d4v acc_t;
+  typedef d4v vec_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * v + q; }
+};
+
+__device__ __forceinline__ d4v mma64(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Four values of G = D + Y * inv_mu at element offsets off[t] (t < nvalid).
+// `contig` means the four offsets are consecutive and 4-aligned.
+template <typename S>
+__device__ __forceinline__ void load_g4(const S* __restrict__ D, const S* __restrict__ Y,
+                                        const int64_t off[4], bool contig, int nvalid, S inv_mu,
+                                        S g[4]) {
+  typedef typename MM<S>::vec_t V;
+  if (contig && nvalid == 4) {
+    V d = *reinterpret_cast<const V*>(D + off[0]);
+    V y = *reinterpret_cast<const V*>(Y + off[0]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g[t] = d[t] + y[t] * inv_mu;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) g[t] = (t < nvalid) ? D[off[t]] + Y[off[t]] * inv_mu : S(0);
+  }
+}
+
+struct GroupIdx {
+  int start[kMaxN + 1];  // first block of each mode
+};
+
+__device__ __forceinline__ int find_mode(const GroupIdx& gi, int N, int blk) {
+  int n = 0;
+  while (n + 1 < N && blk >= gi.start[n + 1]) ++n;
+  return n;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM-P.  Column scheme (B > 1): one block = 64 unfolding columns, its 4 waves
+// split the I_n contraction; lane (p, q) holds columns j0 + 4p .. +3 of row
+// i0 + q.  MFMA t: A[r][k] = U[i0+k][r], B[k][c] = G[i0+k][j0 + 4c + t].
+// Row scheme (B == 1, the last mode): one wave = 16 rows a, lane (p, q) reads
+// G[a0+p][i0+4q .. +3]; A[a][k] = G, B[k][r] = U, all four t accumulate into
+// one tile since they share the output.
+// ---------------------------------------------------------------------------
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_gemm_p(Problem<S> pb, GroupIdx gi) {
+  typedef typename MM<S>::acc_t Acc;
+  if (pb.sc->done) return;
+  const int n = find_mode(gi, pb.N, blockIdx.x);
+  const int64_t tile = blockIdx.x - gi.start[n];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const S inv_mu = S(1.0 / pb.sc->mu);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  const S* __restrict__ Us = mb.Us;
+
+  if (g.B > 1) {
+    __shared__ S red[4][64][16];
+    const int64_t j4 = tile * 64 + 4 * p;
+    int64_t off[4];
+    int nvalid = 0;
+    const bool contig = (g.B % 4) == 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t j = j4 + t;
+      const int64_t jj = j < g.J ? j : 0;
+      const int64_t a = jj / g.B, b = jj - a * g.B;
+      off[t] = a * (int64_t)g.I * g.B + b;
+      nvalid += (j < g.J) ? 1 : 0;
+    }
+    const int rows_per_wave = ((g.I + 15) / 16) * 4;
+    const int kbeg = wave * rows_per_wave;
+    const int kend = min(g.I, kbeg + rows_per_wave);
+    Acc acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = Acc{0, 0, 0, 0};
+    for (int i0 = kbeg; i0 < kend; i0 += 4) {
+      const int i = i0 + q;
+      S gv[4] = {0, 0, 0, 0};
+      S u = 0;
+      if (i < kend) {
+        int64_t o[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) o[t] = off[t] + (int64_t)i * g.B;
+        load_g4<S>(pb.D, mb.Y, o, contig, nvalid, inv_mu, gv);
+        u = Us[(int64_t)i * kRT + p];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u, gv[t], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wave][lane][t * 4 + v] = acc[t][v];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = MM<S>::row(q, v);
+        if (r >= g.R) continue;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (t >= nvalid) continue;
+          S s = red[0][lane][t * 4 + v] + red[1][lane][t * 4 + v] + red[2][lane][t * 4 + v] +
+                red[3][lane][t * 4 + v];
+          mb.P[(int64_t)r * g.J + j4 + t] = s;
+        }
+      }
+    }
+  } else {
+    // Row scheme: rows a = tile*64 + wave*16 + p.
+    const int64_t a0 = tile * 64 + wave * 16;
+    const int64_t arow = a0 + p;
+    const bool rowok = arow < g.A;
+    const bool contig = (g.I % 4) == 0;
+    Acc acc = Acc{0, 0, 0, 0};
+    for (int i0 = 0; i0 < g.I; i0 += 16) {
+      const int i = i0 + 4 * q;
+      const int nv = max(0, min(4, g.I - i));
+      S gv[4] = {0, 0, 0, 0};
+      if (rowok && nv > 0) {
+        int64_t o[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) o[t] = arow * g.I + i + t;
+        load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const S u = (t < nv) ? Us[(int64_t)(i + t) * kRT + p] : S(0);
+        acc = MM<S>::mma(gv[t], u, acc);
+      }
+    }
+    // D[m][n = p] = P[r = p][a0 + m], m = row(q, v)
+    if (p < g.R) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t a = a0 + MM<S>::row(q, v);
+        if (a < g.A) mb.P[(int64_t)p * g.J + a] = acc[v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM-M split-K partials.  Block = 8 waves; the block owns a contiguous
+// range of the contraction (columns j for B > 1, rows a for B == 1) and
+// writes one partial M[I][16] (FP64) after reducing its waves in LDS.
+// Column scheme: K-step = 16 columns, lane (p, q) holds columns j0+4q..+3;
+// for row block ib: A[i][k] = G[16ib + i][col], B[k][r] = P[r][col].
+// Row scheme: K-step = 4 rows a (k = q); lane (p, q) holds G[a0+q][64c+4p..+3];
+// MFMA (c, t): A[m][k] = G[a0+k][64c + 4m + t], B[k][r] = P[r][a0+k].
+// ---------------------------------------------------------------------------
+
+constexpr int kMWaves = 8;
+
+template <typename S>
+__global__ void __launch_bounds__(512) k_gemm_m(Problem<S> pb, GroupIdx gi) {
+  typedef typename MM<S>::acc_t Acc;
+  typedef typename MM<S>::vec_t V;
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int n = find_mode(gi, pb.N, blockIdx.x);
+  const int blk = blockIdx.x - gi.start[n];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const S inv_mu = S(1.0 / pb.sc->mu);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  __shared__ double red[kMWaves][64][4];
+  double* __restrict__ out = mb.Mpart + (int64_t)blk * g.I * kRT;
+
+  if (g.B > 1) {
+    constexpr int IBP = 8;  // row blocks per pass
+    const int64_t nsteps = (g.J + 15) / 16;
+    const int64_t per_blk = (nsteps + mb.mblocks - 1) / mb.mblocks;
+    const int64_t sbeg = (int64_t)blk * per_blk;
+    const int64_t send = min(nsteps, sbeg + per_blk);
+    const bool contig = (g.B % 4) == 0;
+    const bool pvec = (g.J % 4) == 0;
+    const int nib = (g.I + 15) / 16;
+    for (int ib0 = 0; ib0 < nib; ib0 += IBP) {
+      Acc acc[IBP];
+#pragma unroll
+      for (int u = 0; u < IBP; ++u) acc[u] = Acc{0, 0, 0, 0};
+      for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
+        const int64_t j4 = st * 16 + 4 * q;
+        int64_t off[4];
+        int nvalid = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int64_t j = j4 + t;
+          const int64_t jj = j < g.J ? j : 0;
+          const int64_t a = jj / g.B, b = jj - a * g.B;
+          off[t] = a * (int64_t)g.I * g.B + b;
+          nvalid += (j < g.J) ? 1 : 0;
+        }
+        S pv[4] = {0, 0, 0, 0};
+        if (p < g.R) {
+          const S* prow = mb.P + (int64_t)p * g.J;
+          if (pvec && nvalid == 4) {
+            V v = *reinterpret_cast<const V*>(prow + j4);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) pv[t] = v[t];
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) pv[t] = (t < nvalid) ? prow[j4 + t] : S(0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < IBP; ++u) {
+          const int i = (ib0 + u) * 16 + p;
+          if (ib0 + u >= nib) break;
+          S gv[4] = {0, 0, 0, 0};
+          if (i < g.I && nvalid > 0) {
+            int64_t o[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) o[t] = off[t] + (int64_t)i * g.B;
+            load_g4<S>(pb.D, mb.Y, o, contig, nvalid, inv_mu, gv);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[u] = MM<S>::mma(gv[t], pv[t], acc[u]);
+        }
+      }
+      // reduce the waves and write rows i = 16(ib0+u) + 4q + v, column r = p
+      for (int u = 0; u < IBP; ++u) {
+        if (ib0 + u >= nib) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave][lane][v] = (double)acc[u][v];
+        __syncthreads();
+        if (threadIdx.x < 256) {
+          const int l = threadIdx.x >> 2, v = threadIdx.x & 3;
+          double s = 0;
+#pragma unroll
+          for (int w = 0; w < kMWaves; ++w) s += red[w][l][v];
+          const int i = (ib0 + u) * 16 + MM<S>::row(l >> 4, v);
+          if (i < g.I) out[(int64_t)i * kRT + (l & 15)] = s;
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    // rows a, K-step of 4 rows
+    constexpr int CHP = sizeof(S) == 4 ? 4 : 2;  // 64-wide i chunks per pass
+    const int64_t nsteps = (g.A + 3) / 4;
+    const int64_t per_blk = (nsteps + mb.mblocks - 1) / mb.mblocks;
+    const int64_t sbeg = (int64_t)blk * per_blk;
+    const int64_t send = min(nsteps, sbeg + per_blk);
+    const bool contig = (g.I % 4) == 0;
+    const int nch = (g.I + 63) / 64;
+    for (int c0 = 0; c0 < nch; c0 += CHP) {
+      Acc acc[4][4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[c][t] = Acc{0, 0, 0, 0};
+      for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
+        const int64_t a = st * 4 + q;
+        const bool aok = a < g.A;
+        const S pv = (aok && p < g.R) ? mb.P[(int64_t)p * g.J + a] : S(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (c >= CHP || c0 + c >= nch) break;
+          const int i = (c0 + c) * 64 + 4 * p;
+          const int nv = max(0, min(4, g.I - i));
+          S gv[4] = {0, 0, 0, 0};
+          if (aok && nv > 0) {
+            int64_t o[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) o[t] = a * g.I + i + t;
+            load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[c][t] = MM<S>::mma(gv[t], pv, acc[c][t]);
+        }
+      }
+      for (int c = 0; c < 4; ++c) {
+        if (c >= CHP || c0 + c >= nch) break;
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[wave][lane][v] = (double)acc[c][t][v];
+          __syncthreads();
+          if (threadIdx.x < 256) {
+            const int l = threadIdx.x >> 2, v = threadIdx.x & 3;
+            double s = 0;
+#pragma unroll
+            for (int w = 0; w < kMWaves; ++w) s += red[w][l][v];
+            // D[m = row(l>>4, v)][n = l&15] -> i = 64(c0+c) + 4m + t
+            const int m = MM<S>::row(l >> 4, v);
+            const int i = (c0 + c) * 64 + 4 * m + t;
+            if (i < g.I) out[(int64_t)i * kRT + (l & 15)] = s;
+          }
+          __syncthreads();
+        }
+      }
+    }
+  }
+}
+
+// Fixed-order reduction of the GEMM-M partials: M[i][r] = sum_blk Mpart[blk][i][r].
+template <typename S>
+__global__ void __launch_bounds__(256) k_reduce_m(Problem<S> pb, GroupIdx gi) {
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int n = find_mode(gi, pb.N, blockIdx.x);
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int64_t e = (int64_t)(blockIdx.x - gi.start[n]) * 256 + threadIdx.x;
+  const int64_t ne = (int64_t)g.I * kRT;
+  if (e >= ne) return;
+  double s = 0;
+  for (int b = 0; b < mb.mblocks; ++b) s += mb.Mpart[(int64_t)b * ne + e];
+  mb.M[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Gram S = P P^T in FP64 on the f64 MFMA: lane (p, q) holds P[p][c0+4q .. +3];
+// A[m][k] = P[m][col], B[k][n] = P[n][col] are the same register.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_gram(Problem<S> pb, GroupIdx gi) {
+  typedef typename MM<S>::vec_t V;
+  if (pb.sc->done) return;
+  const int n = find_mode(gi, pb.N, blockIdx.x);
+  const int blk = blockIdx.x - gi.start[n];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  __shared__ double red[4][64][4];
+  const int64_t nsteps = (g.J + 15) / 16;
+  const int64_t per_blk = (nsteps + mb.sblocks - 1) / mb.sblocks;
+  const int64_t sbeg = (int64_t)blk * per_blk;
+  const int64_t send = min(nsteps, sbeg + per_blk);
+  const bool pvec = (g.J % 4) == 0;
+  d4v acc = d4v{0, 0, 0, 0};
+  for (int64_t st = sbeg + wave; st < send; st += 4) {
+    const int64_t j4 = st * 16 + 4 * q;
+    double pv[4] = {0, 0, 0, 0};
+    if (p < g.R) {
+      const S* prow = mb.P + (int64_t)p * g.J;
+      if (pvec && j4 + 4 <= g.J) {
+        V v = *reinterpret_cast<const V*>(prow + j4);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pv[t] = (double)v[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pv[t] = (j4 + t < g.J) ? (double)prow[j4 + t] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc = mma64(pv[t], pv[t], acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[v];
+  __syncthreads();
+  if (wave == 0) {
+    double* out = mb.Spart + (int64_t)blk * kRT * kRT;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double s = red[0][lane][v] + red[1][lane][v] + red[2][lane][v] + red[3][lane][v];
+      out[MM<double>::row(q, v) * kRT + p] = s;  // S[row][p]
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+int gemm_m_blocks(const ModeGeom& g) {
+  // enough blocks of 8 waves to keep ~3 waves per CU busy across all modes,
+  // capped by the available K-steps.
+  const int64_t steps = g.B > 1 ? (g.J + 15) / 16 : (g.A + 3) / 4;
+  int64_t want = 96;
+  int64_t maxb = (steps + kMWaves - 1) / kMWaves;
+  return (int)std::max<int64_t>(1, std::min(want, maxb));
+}
+
+int gram_blocks(const ModeGeom& g) {
+  const int64_t steps = (g.J + 15) / 16;
+  int64_t want = 64;
+  int64_t maxb = (steps + 3) / 4;
+  return (int)std::max<int64_t>(1, std::min(want, maxb));
+}
+
+template <typename S>
+void launch_gemm_p(const Problem<S>& p, hipStream_t s) {
+  GroupIdx gi;
+  int tot = 0;
+  for (int n = 0; n < p.N; ++n) {
+    gi.start[n] = tot;
+    const ModeGeom& g = p.g[n];
+    tot += (int)((g.B > 1 ? (g.J + 63) / 64 : (g.A + 63) / 64));
+  }
+  gi.start[p.N] = tot;
+  hipLaunchKernelGGL(k_gemm_p<S>, dim3(tot), dim3(256), 0, s, p, gi);
+}
+
+template <typename S>
+void launch_gemm_m(const Problem<S>& p, hipStream_t s) {
+  GroupIdx gi;
+  int tot = 0;
+  for (int n = 0; n < p.N; ++n) {
+    gi.start[n] = tot;
+    tot += p.m[n].mblocks;
+  }
+  gi.start[p.N] = tot;
+  hipLaunchKernelGGL(k_gemm_m<S>, dim3(tot), dim3(64 * kMWaves), 0, s, p, gi);
+}
+
+template <typename S>
+void launch_reduce_m(const Problem<S>& p, hipStream_t s) {
+  GroupIdx gi;
+  int tot = 0;
+  for (int n = 0; n < p.N; ++n) {
+    gi.start[n] = tot;
+    tot += (int)(((int64_t)p.g[n].I * kRT + 255) / 256);
+  }
+  gi.start[p.N] = tot;
+  hipLaunchKernelGGL(k_reduce_m<S>, dim3(tot), dim3(256), 0, s, p, gi);
+}
+
+template <typename S>
+void launch_gram(const Problem<S>& p, hipStream_t s) {
+  GroupIdx gi;
+  int tot = 0;
+  for (int n = 0; n < p.N; ++n) {
+    gi.start[n] = tot;
+    tot += p.m[n].sblocks;
+  }
+  gi.start[p.N] = tot;
+  hipLaunchKernelGGL(k_gram<S>, dim3(tot), dim3(256), 0, s, p, gi);
+}
+
+template void launch_gemm_p<float>(const Problem<float>&, hipStream_t);
+template void launch_gemm_p<double>(const Problem<double>&, hipStream_t);
+template void launch_gemm_m<float>(const Problem<float>&, hipStream_t);
+template void launch_gemm_m<double>(const Problem<double>&, hipStream_t);
+template void launch_reduce_m<float>(const Problem<float>&, hipStream_t);
+template void launch_reduce_m<double>(const Problem<double>&, hipStream_t);
+template void launch_gram<float>(const Problem<float>&, hipStream_t);
+template void launch_gram<double>(const Problem<double>&, hipStream_t);
+
+}  // namespace pasd

@@ -1,0 +1,677 @@
+// Host runtime behind the C ABI of include/pasd.h: validation, device state,
+// the iteration driver and checkpoint access.  All numerical work is done by
+// the kernels in kernels_*.hip.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pasd.h"
+#include "pasd_internal.hpp"
+
+using namespace pasd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? PASD_ERR_OOM : PASD_ERR_HIP,             \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+constexpr int kIterChunk = 16;  // iterations enqueued between convergence checks
+
+struct Layout {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    const size_t off = total;
+    total += (bytes + 255) / 256 * 256;
+    return off;
+  }
+};
+
+int64_t prod_except(const pasd_config* c, int n) {
+  int64_t p = 1;
+  for (int m = 0; m < c->order; ++m)
+    if (m != n) p *= c->dims[m];
+  return p;
+}
+
+}  // namespace
+
+struct pasd_ctx {
+  pasd_config cfg;
+  int N = 0;
+  int64_t numel = 0;
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  size_t elem = 8;  // bytes per state element
+  ModeGeom geom[kMaxN];
+  double lam[kMaxN];
+  double alpha[kMaxN];
+  int mblocks[kMaxN];
+  int sblocks[kMaxN];
+  void* base = nullptr;
+  size_t bytes = 0;
+  DevScalars* host_sc = nullptr;  // pinned host mirror
+  Problem<float> pf;
+  Problem<double> pd;
+  void* T = nullptr;
+  void* scratch_out = nullptr;  // numel elements, for host exports
+};
+
+namespace {
+
+int validate_impl(const pasd_config* c) {
+  if (!c) return fail(PASD_ERR_INVALID_ARG, "config is NULL");
+  if (c->order < 2 || c->order > PASD_MAX_ORDER)
+    return fail(PASD_ERR_INVALID_ARG, "order must be in [2, " + std::to_string(PASD_MAX_ORDER) + "]");
+  double numel = 1;
+  for (int n = 0; n < c->order; ++n) {
+    if (c->dims[n] < 1) return fail(PASD_ERR_INVALID_ARG, "dims must be >= 1");
+    numel *= (double)c->dims[n];
+  }
+  if (numel > (double)(1LL << 40)) return fail(PASD_ERR_UNSUPPORTED, "tensor too large");
+  for (int n = 0; n < c->order; ++n) {
+    const int64_t J = prod_except(c, n);
+    const int64_t R = c->ranks[n];
+    if (R < 1 || R > c->dims[n] || R > J)
+      return fail(PASD_ERR_INVALID_ARG, "rank R_" + std::to_string(n) +
+                                            " must satisfy 1 <= R_n <= min(I_n, J_n)");
+    if (R > PASD_MAX_RANK)
+      return fail(PASD_ERR_UNSUPPORTED, "rank above " + std::to_string(PASD_MAX_RANK));
+    if (c->dims[n] > (1 << 30)) return fail(PASD_ERR_UNSUPPORTED, "dimension too large");
+    if (c->dims[n] * R > 8192)
+      return fail(PASD_ERR_UNSUPPORTED, "I_n * R_n above 8192 (QR workspace)");
+    if (!isfinite(c->lambda[n]) || !isfinite(c->alpha[n]))
+      return fail(PASD_ERR_INVALID_ARG, "lambda and alpha must be finite");
+  }
+  if (!(c->mu0 > 0) || !isfinite(c->mu0)) return fail(PASD_ERR_INVALID_ARG, "mu0 must be > 0");
+  if (!(c->mu_max >= c->mu0) || !isfinite(c->mu_max))
+    return fail(PASD_ERR_INVALID_ARG, "mu_max must be >= mu0");
+  if (!(c->rho >= 1.0) || !isfinite(c->rho)) return fail(PASD_ERR_INVALID_ARG, "rho must be >= 1");
+  if (!(c->tol >= 0.0) || !isfinite(c->tol)) return fail(PASD_ERR_INVALID_ARG, "tol must be >= 0");
+  if (c->max_iter < 1) return fail(PASD_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (c->precision != PASD_FP64 && c->precision != PASD_FP32 && c->precision != PASD_BF16_GEMM)
+    return fail(PASD_ERR_INVALID_ARG, "unknown precision");
+  if (c->precision == PASD_BF16_GEMM)
+    return fail(PASD_ERR_UNSUPPORTED, "PASD_BF16_GEMM is not available in this build");
+  return PASD_OK;
+}
+
+// Buffer plan shared by pasd_footprint and pasd_create.
+struct Plan {
+  Layout L;
+  size_t off_T, off_D, off_sc, off_hist;
+  size_t off_Y[kMaxN], off_P[kMaxN], off_U[kMaxN], off_Us[kMaxN], off_Uf[kMaxN], off_UfT[kMaxN],
+      off_Mpart[kMaxN], off_M[kMaxN], off_Spart[kMaxN], off_Wf[kMaxN], off_Wev[kMaxN];
+  ModeGeom geom[kMaxN];
+  int mblocks[kMaxN], sblocks[kMaxN];
+  int64_t numel;
+};
+
+void make_plan(const pasd_config* c, Plan& p) {
+  const int N = c->order;
+  const size_t es = c->precision == PASD_FP64 ? 8 : 4;
+  int64_t numel = 1;
+  for (int n = 0; n < N; ++n) numel *= c->dims[n];
+  p.numel = numel;
+  for (int n = 0; n < N; ++n) {
+    ModeGeom& g = p.geom[n];
+    g.A = 1;
+    for (int m = 0; m < n; ++m) g.A *= c->dims[m];
+    g.B = 1;
+    for (int m = n + 1; m < N; ++m) g.B *= c->dims[m];
+    g.I = (int)c->dims[n];
+    g.J = g.A * g.B;
+    g.R = (int)c->ranks[n];
+    p.mblocks[n] = gemm_m_blocks(g);
+    p.sblocks[n] = gram_blocks(g);
+  }
+  p.off_T = p.L.add(numel * es);
+  p.off_D = p.L.add(numel * es);
+  p.off_sc = p.L.add(sizeof(DevScalars));
+  p.off_hist = p.L.add(sizeof(double) * (size_t)c->max_iter * N);
+  for (int n = 0; n < N; ++n) {
+    const ModeGeom& g = p.geom[n];
+    p.off_Y[n] = p.L.add(numel * es);
+    p.off_P[n] = p.L.add((size_t)g.R * g.J * es);
+    p.off_U[n] = p.L.add((size_t)g.I * g.R * 8);
+    p.off_Us[n] = p.L.add((size_t)g.I * kRT * es);
+    p.off_Uf[n] = p.L.add((size_t)g.I * kRT * es);
+    p.off_UfT[n] = p.L.add((size_t)g.I * kRT * es);
+    p.off_Mpart[n] = p.L.add((size_t)p.mblocks[n] * g.I * kRT * 8);
+    p.off_M[n] = p.L.add((size_t)g.I * kRT * 8);
+    p.off_Spart[n] = p.L.add((size_t)p.sblocks[n] * kRT * kRT * 8);
+    p.off_Wf[n] = p.L.add(kRT * kRT * 8);
+    p.off_Wev[n] = p.L.add(kRT * kRT * 8);
+  }
+}
+
+template <typename S>
+void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
+  char* b = static_cast<char*>(ctx->base);
+  memset(&p, 0, sizeof(p));
+  p.N = ctx->N;
+  p.numel = ctx->numel;
+  p.T = reinterpret_cast<const S*>(b + pl.off_T);
+  p.D = reinterpret_cast<S*>(b + pl.off_D);
+  p.sc = reinterpret_cast<DevScalars*>(b + pl.off_sc);
+  p.hist = reinterpret_cast<double*>(b + pl.off_hist);
+  for (int n = 0; n < ctx->N; ++n) {
+    p.g[n] = pl.geom[n];
+    ModeBufs<S>& m = p.m[n];
+    m.Y = reinterpret_cast<S*>(b + pl.off_Y[n]);
+    m.P = reinterpret_cast<S*>(b + pl.off_P[n]);
+    m.U = reinterpret_cast<double*>(b + pl.off_U[n]);
+    m.Us = reinterpret_cast<S*>(b + pl.off_Us[n]);
+    m.Uf = reinterpret_cast<S*>(b + pl.off_Uf[n]);
+    m.UfT = reinterpret_cast<S*>(b + pl.off_UfT[n]);
+    m.Mpart = reinterpret_cast<double*>(b + pl.off_Mpart[n]);
+    m.M = reinterpret_cast<double*>(b + pl.off_M[n]);
+    m.Spart = reinterpret_cast<double*>(b + pl.off_Spart[n]);
+    m.Wf = reinterpret_cast<double*>(b + pl.off_Wf[n]);
+    m.Wev = reinterpret_cast<double*>(b + pl.off_Wev[n]);
+    m.mblocks = pl.mblocks[n];
+    m.sblocks = pl.sblocks[n];
+    p.lam[n] = ctx->lam[n];
+    p.alpha[n] = ctx->alpha[n];
+  }
+  p.mu_max = ctx->cfg.mu_max;
+  p.rho = ctx->cfg.rho;
+  p.tol = ctx->cfg.tol;
+  p.max_iter = ctx->cfg.max_iter;
+  p.precision = ctx->cfg.precision;
+}
+
+// Enqueue `count` iterations; with `ev` non-null an event is recorded before
+// the first launch and after every launch (ev[it * PASD_NUM_KERNELS + k + 1]).
+template <typename S>
+void enqueue_iterations(const Problem<S>& p, int count, hipStream_t s, hipEvent_t* ev) {
+  if (ev) (void)hipEventRecord(ev[0], s);
+  for (int it = 0; it < count; ++it) {
+    hipEvent_t* e = ev ? ev + (size_t)it * PASD_NUM_KERNELS + 1 : nullptr;
+    launch_gemm_m<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_GEMM_M], s);
+    launch_reduce_m<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_REDUCE_M], s);
+    launch_qr<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_QR], s);
+    launch_gemm_p<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_GEMM_P], s);
+    launch_gram<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_GRAM], s);
+    launch_eig<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_EIG], s);
+    launch_fused<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_FUSED], s);
+    launch_control<S>(p, s);
+    if (e) (void)hipEventRecord(e[PASD_K_CONTROL], s);
+  }
+}
+
+int enqueue(pasd_ctx* ctx, int count, hipEvent_t* ev = nullptr) {
+  if (ctx->cfg.precision == PASD_FP64)
+    enqueue_iterations<double>(ctx->pd, count, ctx->stream, ev);
+  else
+    enqueue_iterations<float>(ctx->pf, count, ctx->stream, ev);
+  HIP_TRY(hipGetLastError());
+  return PASD_OK;
+}
+
+int read_scalars(pasd_ctx* ctx) {
+  DevScalars* dsc = ctx->cfg.precision == PASD_FP64 ? ctx->pd.sc : ctx->pf.sc;
+  HIP_TRY(hipMemcpyAsync(ctx->host_sc, dsc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PASD_OK;
+}
+
+void fill_info(pasd_ctx* ctx, pasd_info* info) {
+  memset(info, 0, sizeof(*info));
+  const DevScalars* s = ctx->host_sc;
+  info->iterations = s->k;
+  info->converged = s->converged;
+  info->done = s->done;
+  info->mu = s->mu;
+  for (int n = 0; n < ctx->N; ++n) {
+    info->residual[n] = s->residual[n];
+    info->rank[n] = s->rank[n];
+  }
+  info->bytes_resident = ctx->bytes;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int copy_kind(int on_device) { return on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+
+}  // namespace
+
+extern "C" {
+
+int pasd_config_init(pasd_config* cfg) {
+  if (!cfg) return fail(PASD_ERR_INVALID_ARG, "config is NULL");
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->mu0 = 1e-4;
+  cfg->mu_max = 1e10;
+  cfg->rho = 1.1;
+  cfg->tol = 1e-5;
+  cfg->max_iter = 1000;
+  cfg->precision = PASD_FP64;
+  cfg->device = -1;
+  cfg->stream = nullptr;
+  return PASD_OK;
+}
+
+int pasd_validate(const pasd_config* cfg) {
+  g_last_error.clear();
+  return validate_impl(cfg);
+}
+
+int pasd_footprint(const pasd_config* cfg, size_t* bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(PASD_ERR_INVALID_ARG, "bytes is NULL");
+  const int rc = validate_impl(cfg);
+  if (rc != PASD_OK) return rc;
+  Plan pl;
+  make_plan(cfg, pl);
+  *bytes = pl.L.total + (size_t)pl.numel * (cfg->precision == PASD_FP64 ? 8 : 4);
+  return PASD_OK;
+}
+
+int pasd_create(const pasd_config* cfg, const void* T, int T_on_device, pasd_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(PASD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate_impl(cfg);
+  if (rc != PASD_OK) return rc;
+  if (!T) return fail(PASD_ERR_INVALID_ARG, "T is NULL");
+  pasd_ctx* ctx = new pasd_ctx();
+  ctx->cfg = *cfg;
+  ctx->N = cfg->order;
+  int dev = cfg->device;
+  if (dev < 0) {
+    if (hipGetDevice(&dev) != hipSuccess) {
+      delete ctx;
+      return fail(PASD_ERR_HIP, "hipGetDevice failed (no GPU?)");
+    }
+  }
+  ctx->dev = dev;
+  ctx->stream = static_cast<hipStream_t>(cfg->stream);
+  ctx->elem = cfg->precision == PASD_FP64 ? 8 : 4;
+  Plan pl;
+  make_plan(cfg, pl);
+  ctx->numel = pl.numel;
+  const int64_t numel = pl.numel;
+  for (int n = 0; n < ctx->N; ++n) {
+    const double J = (double)prod_except(cfg, n);
+    ctx->geom[n] = pl.geom[n];
+    ctx->lam[n] = cfg->lambda[n] > 0 ? cfg->lambda[n]
+                                     : sqrt(std::max((double)cfg->dims[n], J)) / ctx->N;
+    ctx->mblocks[n] = pl.mblocks[n];
+    ctx->sblocks[n] = pl.sblocks[n];
+  }
+  for (int n = 0; n < ctx->N; ++n) ctx->alpha[n] = cfg->alpha[n] > 0 ? cfg->alpha[n] : ctx->lam[n];
+  DeviceGuard guard(dev);
+  hipError_t e = hipMalloc(&ctx->base, pl.L.total);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(e == hipErrorOutOfMemory ? PASD_ERR_OOM : PASD_ERR_HIP,
+                std::string("hipMalloc of solver state: ") + hipGetErrorString(e));
+  }
+  e = hipMalloc(&ctx->scratch_out, (size_t)numel * ctx->elem);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_sc, sizeof(DevScalars), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    pasd_destroy(ctx);
+    return fail(e == hipErrorOutOfMemory ? PASD_ERR_OOM : PASD_ERR_HIP,
+                std::string("allocation: ") + hipGetErrorString(e));
+  }
+  ctx->bytes = pl.L.total + (size_t)numel * ctx->elem;
+  ctx->T = static_cast<char*>(ctx->base) + pl.off_T;
+  if (cfg->precision == PASD_FP64)
+    fill_problem<double>(ctx, pl, ctx->pd);
+  else
+    fill_problem<float>(ctx, pl, ctx->pf);
+  e = hipMemcpyAsync(ctx->T, T, (size_t)numel * ctx->elem, (hipMemcpyKind)copy_kind(T_on_device),
+                     ctx->stream);
+  if (e != hipSuccess) {
+    pasd_destroy(ctx);
+    return fail(PASD_ERR_HIP, std::string("copy of T: ") + hipGetErrorString(e));
+  }
+  rc = pasd_reset(ctx);
+  if (rc == PASD_OK) {
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) rc = fail(PASD_ERR_HIP, std::string("create: ") + hipGetErrorString(e));
+  }
+  if (rc != PASD_OK) {
+    pasd_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return PASD_OK;
+}
+
+int pasd_reset(pasd_ctx* ctx) {
+  if (!ctx) return fail(PASD_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard guard(ctx->dev);
+  if (ctx->cfg.precision == PASD_FP64)
+    launch_init<double>(ctx->pd, ctx->cfg.mu0, ctx->stream);
+  else
+    launch_init<float>(ctx->pf, ctx->cfg.mu0, ctx->stream);
+  HIP_TRY(hipGetLastError());
+  return PASD_OK;
+}
+
+int pasd_step(pasd_ctx* ctx, int n_iters) {
+  g_last_error.clear();
+  if (!ctx) return fail(PASD_ERR_INVALID_ARG, "ctx is NULL");
+  if (n_iters < 0) return fail(PASD_ERR_INVALID_ARG, "n_iters must be >= 0");
+  DeviceGuard guard(ctx->dev);
+  return enqueue(ctx, n_iters);
+}
+
+int pasd_query(pasd_ctx* ctx, pasd_info* info) {
+  g_last_error.clear();
+  if (!ctx || !info) return fail(PASD_ERR_INVALID_ARG, "ctx or info is NULL");
+  DeviceGuard guard(ctx->dev);
+  int rc = read_scalars(ctx);
+  if (rc != PASD_OK) return rc;
+  fill_info(ctx, info);
+  return PASD_OK;
+}
+
+int pasd_solve(pasd_ctx* ctx, pasd_info* info) {
+  g_last_error.clear();
+  if (!ctx) return fail(PASD_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard guard(ctx->dev);
+  for (;;) {
+    int rc = read_scalars(ctx);
+    if (rc != PASD_OK) return rc;
+    if (ctx->host_sc->done) break;
+    const int left = ctx->cfg.max_iter - ctx->host_sc->k;
+    rc = enqueue(ctx, std::max(1, std::min(kIterChunk, left)));
+    if (rc != PASD_OK) return rc;
+  }
+  if (info) fill_info(ctx, info);
+  switch (ctx->host_sc->done) {
+    case 1: return PASD_OK;
+    case 2: return PASD_NOT_CONVERGED;
+    default: return fail(PASD_ERR_NUMERIC, "NaN or infinity in the iteration");
+  }
+}
+
+int pasd_get_result(pasd_ctx* ctx, void* X, void* E, int on_device) {
+  g_last_error.clear();
+  if (!ctx) return fail(PASD_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard guard(ctx->dev);
+  const size_t bytes = (size_t)ctx->numel * ctx->elem;
+  for (int which = 0; which < 2; ++which) {
+    void* dst = which == 0 ? X : E;
+    if (!dst) continue;
+    void* tgt = on_device ? dst : ctx->scratch_out;
+    if (ctx->cfg.precision == PASD_FP64)
+      launch_output<double>(ctx->pd, which == 0 ? (double*)tgt : nullptr,
+                            which == 1 ? (double*)tgt : nullptr, ctx->stream);
+    else
+      launch_output<float>(ctx->pf, which == 0 ? (float*)tgt : nullptr,
+                           which == 1 ? (float*)tgt : nullptr, ctx->stream);
+    HIP_TRY(hipGetLastError());
+    if (!on_device)
+      HIP_TRY(hipMemcpyAsync(dst, ctx->scratch_out, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  return PASD_OK;
+}
+
+int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
+  g_last_error.clear();
+  if (!ctx || !dst) return fail(PASD_ERR_INVALID_ARG, "ctx or dst is NULL");
+  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_Z || q == PASD_Q_U || q == PASD_Q_P || q == PASD_Q_UF;
+  if (per_mode && (index < 0 || index >= ctx->N)) return fail(PASD_ERR_INVALID_ARG, "mode index out of range");
+  DeviceGuard guard(ctx->dev);
+  const bool f64 = ctx->cfg.precision == PASD_FP64;
+  const size_t es = ctx->elem;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  switch (q) {
+    case PASD_Q_E:
+    case PASD_Q_X:
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      return q == PASD_Q_E ? pasd_get_result(ctx, nullptr, dst, on_device)
+                           : pasd_get_result(ctx, dst, nullptr, on_device);
+    case PASD_Q_Y:
+      src = f64 ? (const void*)ctx->pd.m[index].Y : (const void*)ctx->pf.m[index].Y;
+      bytes = (size_t)ctx->numel * es;
+      break;
+    case PASD_Q_D:
+      src = f64 ? (const void*)ctx->pd.D : (const void*)ctx->pf.D;
+      bytes = (size_t)ctx->numel * es;
+      break;
+    case PASD_Q_Z: {
+      void* tgt = on_device ? dst : ctx->scratch_out;
+      if (f64)
+        launch_component<double>(ctx->pd, index, (double*)tgt, ctx->stream);
+      else
+        launch_component<float>(ctx->pf, index, (float*)tgt, ctx->stream);
+      HIP_TRY(hipGetLastError());
+      if (on_device) {
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        return PASD_OK;
+      }
+      src = ctx->scratch_out;
+      bytes = (size_t)ctx->numel * es;
+      break;
+    }
+    case PASD_Q_U:
+      src = f64 ? (const void*)ctx->pd.m[index].U : (const void*)ctx->pf.m[index].U;
+      bytes = (size_t)ctx->geom[index].I * ctx->geom[index].R * 8;
+      break;
+    case PASD_Q_P:
+      src = f64 ? (const void*)ctx->pd.m[index].P : (const void*)ctx->pf.m[index].P;
+      bytes = (size_t)ctx->geom[index].R * ctx->geom[index].J * es;
+      break;
+    case PASD_Q_UF: {
+      // I x kRT padded state-type copy -> I x R double
+      const ModeGeom& g = ctx->geom[index];
+      std::vector<char> tmp((size_t)g.I * kRT * es);
+      const void* s = f64 ? (const void*)ctx->pd.m[index].Uf : (const void*)ctx->pf.m[index].Uf;
+      HIP_TRY(hipMemcpyAsync(tmp.data(), s, tmp.size(), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      std::vector<double> outv((size_t)g.I * g.R);
+      for (int i = 0; i < g.I; ++i)
+        for (int r = 0; r < g.R; ++r)
+          outv[(size_t)i * g.R + r] = f64 ? ((const double*)tmp.data())[(size_t)i * kRT + r]
+                                          : (double)((const float*)tmp.data())[(size_t)i * kRT + r];
+      HIP_TRY(hipMemcpy(dst, outv.data(), outv.size() * 8,
+                        on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+      return PASD_OK;
+    }
+    case PASD_Q_SCALARS: {
+      int rc = read_scalars(ctx);
+      if (rc != PASD_OK) return rc;
+      double v[2] = {(double)ctx->host_sc->k, ctx->host_sc->mu};
+      HIP_TRY(hipMemcpy(dst, v, sizeof(v), on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+      return PASD_OK;
+    }
+    default:
+      return fail(PASD_ERR_INVALID_ARG, "unknown quantity");
+  }
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, kind, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PASD_OK;
+}
+
+int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device) {
+  g_last_error.clear();
+  if (!ctx || !src) return fail(PASD_ERR_INVALID_ARG, "ctx or src is NULL");
+  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_U || q == PASD_Q_P;
+  if (per_mode && (index < 0 || index >= ctx->N)) return fail(PASD_ERR_INVALID_ARG, "mode index out of range");
+  DeviceGuard guard(ctx->dev);
+  const bool f64 = ctx->cfg.precision == PASD_FP64;
+  const size_t es = ctx->elem;
+  const hipMemcpyKind kind = (hipMemcpyKind)copy_kind(on_device);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  switch (q) {
+    case PASD_Q_E: {
+      // D = T - E, computed on the host side of the copy to keep one code path
+      const size_t bytes = (size_t)ctx->numel * es;
+      std::vector<char> e(bytes), t(bytes);
+      HIP_TRY(hipMemcpy(e.data(), src, bytes, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+      HIP_TRY(hipMemcpy(t.data(), ctx->T, bytes, hipMemcpyDeviceToHost));
+      for (int64_t x = 0; x < ctx->numel; ++x) {
+        if (f64)
+          ((double*)e.data())[x] = ((double*)t.data())[x] - ((double*)e.data())[x];
+        else
+          ((float*)e.data())[x] = ((float*)t.data())[x] - ((float*)e.data())[x];
+      }
+      void* D = f64 ? (void*)ctx->pd.D : (void*)ctx->pf.D;
+      HIP_TRY(hipMemcpy(D, e.data(), bytes, hipMemcpyHostToDevice));
+      return PASD_OK;
+    }
+    case PASD_Q_Y: {
+      void* d = f64 ? (void*)ctx->pd.m[index].Y : (void*)ctx->pf.m[index].Y;
+      HIP_TRY(hipMemcpy(d, src, (size_t)ctx->numel * es, kind));
+      return PASD_OK;
+    }
+    case PASD_Q_D: {
+      void* d = f64 ? (void*)ctx->pd.D : (void*)ctx->pf.D;
+      HIP_TRY(hipMemcpy(d, src, (size_t)ctx->numel * es, kind));
+      return PASD_OK;
+    }
+    case PASD_Q_U: {
+      const ModeGeom& g = ctx->geom[index];
+      std::vector<double> u((size_t)g.I * g.R);
+      HIP_TRY(hipMemcpy(u.data(), src, u.size() * 8, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+      void* d = f64 ? (void*)ctx->pd.m[index].U : (void*)ctx->pf.m[index].U;
+      HIP_TRY(hipMemcpy(d, u.data(), u.size() * 8, hipMemcpyHostToDevice));
+      std::vector<char> us((size_t)g.I * kRT * es, 0);
+      for (int i = 0; i < g.I; ++i)
+        for (int r = 0; r < g.R; ++r) {
+          if (f64)
+            ((double*)us.data())[(size_t)i * kRT + r] = u[(size_t)i * g.R + r];
+          else
+            ((float*)us.data())[(size_t)i * kRT + r] = (float)u[(size_t)i * g.R + r];
+        }
+      void* ds = f64 ? (void*)ctx->pd.m[index].Us : (void*)ctx->pf.m[index].Us;
+      HIP_TRY(hipMemcpy(ds, us.data(), us.size(), hipMemcpyHostToDevice));
+      return PASD_OK;
+    }
+    case PASD_Q_P: {
+      void* d = f64 ? (void*)ctx->pd.m[index].P : (void*)ctx->pf.m[index].P;
+      HIP_TRY(hipMemcpy(d, src, (size_t)ctx->geom[index].R * ctx->geom[index].J * es, kind));
+      return PASD_OK;
+    }
+    case PASD_Q_SCALARS: {
+      double v[2];
+      HIP_TRY(hipMemcpy(v, src, sizeof(v), on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+      if (!(v[1] > 0) || v[0] < 0 || v[0] > ctx->cfg.max_iter)
+        return fail(PASD_ERR_INVALID_ARG, "scalars must hold 0 <= k <= max_iter and mu > 0");
+      int rc = read_scalars(ctx);
+      if (rc != PASD_OK) return rc;
+      DevScalars s = *ctx->host_sc;
+      s.k = (int)v[0];
+      s.mu = v[1];
+      s.done = s.k >= ctx->cfg.max_iter ? 2 : 0;
+      s.converged = 0;
+      for (int n = 0; n < kMaxN; ++n) s.res_bits[n] = 0;
+      DevScalars* dsc = f64 ? ctx->pd.sc : ctx->pf.sc;
+      HIP_TRY(hipMemcpy(dsc, &s, sizeof(s), hipMemcpyHostToDevice));
+      return PASD_OK;
+    }
+    default:
+      return fail(PASD_ERR_INVALID_ARG, "quantity cannot be imported");
+  }
+}
+
+int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
+  g_last_error.clear();
+  if (count < 0 || (count > 0 && !ctxs)) return fail(PASD_ERR_INVALID_ARG, "bad context list");
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return fail(PASD_ERR_INVALID_ARG, "NULL context in batch");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(PASD_ERR_INVALID_ARG, "context repeated in batch");
+    if (ctxs[i]->dev != ctxs[0]->dev) return fail(PASD_ERR_INVALID_ARG, "contexts on different devices");
+  }
+  for (int i = 0; i < count; ++i) {
+    int rc = pasd_step(ctxs[i], n_iters);
+    if (rc != PASD_OK) return rc;
+  }
+  return PASD_OK;
+}
+
+int pasd_profile(pasd_ctx* ctx, int n_iters, double* ms, int* launches) {
+  g_last_error.clear();
+  if (!ctx || !ms) return fail(PASD_ERR_INVALID_ARG, "ctx or ms is NULL");
+  if (n_iters < 1 || n_iters > 100000) return fail(PASD_ERR_INVALID_ARG, "n_iters out of range");
+  DeviceGuard guard(ctx->dev);
+  for (int k = 0; k < PASD_NUM_KERNELS; ++k) {
+    ms[k] = 0;
+    if (launches) launches[k] = 0;
+  }
+  const size_t nev = (size_t)n_iters * PASD_NUM_KERNELS + 1;
+  std::vector<hipEvent_t> ev(nev, nullptr);
+  int rc = PASD_OK;
+  size_t made = 0;
+  for (; made < nev; ++made) {
+    hipError_t e = hipEventCreate(&ev[made]);
+    if (e != hipSuccess) {
+      rc = fail(PASD_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e));
+      break;
+    }
+  }
+  if (rc == PASD_OK) rc = enqueue(ctx, n_iters, ev.data());
+  if (rc == PASD_OK) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) rc = fail(PASD_ERR_HIP, std::string("profile: ") + hipGetErrorString(e));
+  }
+  if (rc == PASD_OK) {
+    for (int it = 0; it < n_iters; ++it)
+      for (int k = 0; k < PASD_NUM_KERNELS; ++k) {
+        const size_t i = (size_t)it * PASD_NUM_KERNELS + k;
+        float t = 0;
+        if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) == hipSuccess) ms[k] += t;
+        if (launches) launches[k] += 1;
+      }
+  }
+  for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
+  return rc;
+}
+
+void pasd_destroy(pasd_ctx* ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard guard(ctx->dev);
+    if (ctx->base || ctx->scratch_out) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->base) (void)hipFree(ctx->base);
+    if (ctx->scratch_out) (void)hipFree(ctx->scratch_out);
+    if (ctx->host_sc) (void)hipHostFree(ctx->host_sc);
+  }
+  delete ctx;
+}
+
+const char* pasd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
