@@ -92,6 +92,7 @@ typedef struct {
   int rank[PASD_MAX_ORDER];         /* #{singular values of U_n^T G_n above lambda_n/mu}
                                        in the last SVT, per mode */
   size_t bytes_resident;            /* device memory held by the context */
+  int eig_sweeps[PASD_MAX_ORDER];   /* Jacobi sweeps of the last Gram eigensolve, per mode */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;
@@ -107,8 +108,10 @@ enum pasd_quantity {
   PASD_Q_UF = 6,     /* U_n W_n with W_n the R_n x R_n SVT factor (V_n = W_n P_n),
                         I_n x R_n row-major, double, export only */
   PASD_Q_SCALARS = 7, /* double[2] = {k, mu} */
-  PASD_Q_D = 8        /* D = T - E as the solver stores it (numel, state dtype); a
+  PASD_Q_D = 8,       /* D = T - E as the solver stores it (numel, state dtype); a
                          checkpoint of D (not E) restores the iterate bitwise */
+  PASD_Q_WEV = 9      /* eigenvectors of the last Gram P_n P_n^T, the starting basis
+                         of the next eigensolve: R_n x R_n row-major, double */
 };
 
 /* Fill cfg with defaults (order 0, no dims).  Host only. */
@@ -154,10 +157,11 @@ int pasd_get_result(pasd_ctx *ctx, void *X, void *E, int on_device);
  * applies).  Synchronising. */
 int pasd_export(pasd_ctx *ctx, int quantity, int index, void *dst, int dst_on_device);
 
-/* Overwrite one quantity (E or D, Y_n, U_n, P_n or the scalars) for
- * checkpoint restore.  A restore of D, every Y_n, U_n, P_n and the scalars
- * reproduces the saved iterate bitwise (E is converted to D = T - E, which is
- * exact only up to rounding).  Synchronising. */
+/* Overwrite one quantity (E or D, Y_n, U_n, P_n, the eigenbasis or the
+ * scalars) for checkpoint restore.  A restore of D, every Y_n, U_n, P_n, the
+ * eigenbases and the scalars reproduces the saved iterate bitwise (E is
+ * converted to D = T - E, which is exact only up to rounding; without the
+ * eigenbases the continuation agrees to rounding).  Synchronising. */
 int pasd_import(pasd_ctx *ctx, int quantity, int index, const void *src, int src_on_device);
 
 /* Step several contexts together (serving): n_iters iterations of each,

@@ -6,5 +6,6 @@ ctypes binding (pasd.py).
 """
 
 from .pasd import (  # noqa: F401
-    BF16_GEMM, FP32, FP64, PasdError, Q_D, Q_E, Q_P, Q_SCALARS, Q_U, Q_UF, Q_X, Q_Y, Q_Z, Solver,
+    BF16_GEMM, FP32, FP64, PasdError, Q_D, Q_E, Q_P, Q_SCALARS, Q_U, Q_UF, Q_WEV, Q_X, Q_Y, Q_Z,
+    Solver,
     footprint, lib, make_config, step_batch, validate)

@@ -84,8 +84,82 @@ __device__ __forceinline__ S nanmax(S a, S b) {
   return (b > a || b != b) ? b : a;
 }
 
-template <typename S, int NN, int VEC>
-__global__ void __launch_bounds__(256) k_fused(Problem<S> pb) {
+// Block-wide maximum of the per-thread residual maxima (blockDim = 256), one
+// atomicMax per block and mode on slot blockIdx % kResSlots.  Max is exact, so
+// the result does not depend on the order.  NaN propagates (its bit pattern
+// exceeds every finite non-negative double).
+template <int NN, typename S>
+__device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rmax)[NN]) {
+  __shared__ double red[4][NN];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    double r = (double)rmax[n];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r = nanmax(r, __shfl_xor(r, o, 64));
+    if (lane == 0) red[wave][n] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < NN) {
+    const int n = threadIdx.x;
+    const double r = nanmax(nanmax(red[0][n], red[1][n]), nanmax(red[2][n], red[3][n]));
+    atomicMax(&sc->res_slots[n][blockIdx.x % kResSlots], (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// Row view of the tensor for the fused pass: rows = numel / I_N of length I_N.
+// For a mode n < N-1 the row index splits as row = (a * I_n + i_n) * Rb_n + rb
+// with Rb_n = B_n / I_N, and the unfolding column is j = a * B_n + rb * I_N + i.
+struct RowGeom {
+  uint64_t Q;        // VEC-chunks per row (I_N / VEC)
+  uint64_t IN;       // I_N
+  uint64_t Rb[kMaxN];
+};
+
+// Z_n at the VEC elements starting at column i of `row`, with the rank loop
+// unrolled to RP (P_n has zero rows up to kRT, U_n W_n zero columns), so that
+// all loads of P_n and U_n W_n are independent and issue together.
+template <typename S, int VEC, int RP, typename IT>
+__device__ __forceinline__ void recon_row(const Problem<S>& pb, const RowGeom& rg, int n, bool last,
+                                          IT row, IT i, S z[VEC]) {
+  const ModeGeom& g = pb.g[n];
+  const ModeBufs<S>& mb = pb.m[n];
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) z[t] = S(0);
+  if (last) {
+    S pr[RP];
+    S u[RP][VEC];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      pr[r] = mb.P[(int64_t)r * g.J + row];
+      loadv<S, VEC>(mb.UfT + (int64_t)r * g.I, i, u[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RP; ++r)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) z[t] += u[r][t] * pr[r];
+  } else {
+    const IT Rb = (IT)rg.Rb[n];
+    const IT q1 = Rb == 1 ? row : row / Rb;
+    const IT a = g.A == 1 ? IT(0) : q1 / (IT)g.I;
+    const IT in = q1 - a * (IT)g.I;
+    const IT j = a * (IT)g.B + (row - q1 * Rb) * (IT)rg.IN + i;
+    S u[RP];
+    S pv[RP][VEC];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      u[r] = mb.Uf[(int64_t)in * kRT + r];
+      loadv<S, VEC>(mb.P + (int64_t)r * g.J, j, pv[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RP; ++r)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) z[t] += u[r] * pv[r][t];
+  }
+}
+
+template <typename S, int NN, int VEC, int RP, typename IT>
+__global__ void __launch_bounds__(256) k_fused(Problem<S> pb, RowGeom rg) {
   if (pb.sc->done) return;
   const double mu_d = pb.sc->mu;
   const S mu = (S)mu_d;
@@ -95,17 +169,19 @@ __global__ void __launch_bounds__(256) k_fused(Problem<S> pb) {
   S rmax[NN];
 #pragma unroll
   for (int n = 0; n < NN; ++n) rmax[n] = S(0);
-  const int64_t nchunk = pb.numel / VEC;
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nchunk;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t x0 = c * VEC;
+  const IT nchunk = (IT)(pb.numel / VEC);
+  const IT Q = (IT)rg.Q;
+  for (IT c = (IT)blockIdx.x * blockDim.x + threadIdx.x; c < nchunk; c += (IT)gridDim.x * blockDim.x) {
+    const IT row = c / Q;
+    const IT i = (c - row * Q) * VEC;
+    const IT x0 = c * VEC;
     S tv[VEC];
     loadv<S, VEC>(pb.T, x0, tv);
     S z[NN][VEC];
     S y[NN][VEC];
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      recon<S, VEC>(pb, n, x0, z[n]);
+      recon_row<S, VEC, RP, IT>(pb, rg, n, n == NN - 1, row, i, z[n]);
       loadv<S, VEC>(pb.m[n].Y, x0, y[n]);
     }
     S dv[VEC];
@@ -129,24 +205,31 @@ __global__ void __launch_bounds__(256) k_fused(Problem<S> pb) {
 #pragma unroll
     for (int n = 0; n < NN; ++n) storev<S, VEC>(pb.m[n].Y, x0, y[n]);
   }
-#pragma unroll
-  for (int n = 0; n < NN; ++n) {
-    double r = (double)rmax[n];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) r = nanmax(r, __shfl_xor(r, o, 64));
-    if ((threadIdx.x & 63) == 0)
-      atomicMax(&pb.sc->res_bits[n], (unsigned long long)__double_as_longlong(r));
-  }
+  block_residual_max<NN>(pb.sc, rmax);
 }
 
+// One wave: fold the residual slots (and clear them for the next iteration),
+// then lane 0 applies Algorithm 1, lines 7-8.
 template <typename S>
-__global__ void k_control(Problem<S> pb) {
+__global__ void __launch_bounds__(64) k_control(Problem<S> pb) {
   DevScalars* sc = pb.sc;
   if (sc->done) return;
+  __shared__ double res[kMaxN];
+  const int lane = threadIdx.x;
+  for (int n = 0; n < pb.N; ++n) {
+    unsigned long long b = sc->res_slots[n][lane];
+    sc->res_slots[n][lane] = 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const unsigned long long other = __shfl_xor(b, o, 64);
+      b = other > b ? other : b;
+    }
+    if (lane == 0) res[n] = __longlong_as_double((long long)b);
+  }
+  if (lane != 0) return;
   bool conv = true, bad = false;
   for (int n = 0; n < pb.N; ++n) {
-    const double r = __longlong_as_double((long long)sc->res_bits[n]);
-    sc->res_bits[n] = 0ull;
+    const double r = res[n];
     sc->residual[n] = r;
     pb.hist[(int64_t)sc->k * pb.N + n] = r;
     if (!(r < pb.tol)) conv = false;
@@ -192,11 +275,14 @@ __global__ void __launch_bounds__(256) k_init_small(Problem<S> pb, double mu0) {
     sc->done = 0;
     sc->converged = 0;
     for (int m = 0; m < kMaxN; ++m) {
-      sc->res_bits[m] = 0ull;
       sc->residual[m] = 0.0;
       sc->rank[m] = 0;
+      sc->eig_sweeps[m] = 0;
     }
   }
+  if (n == 0)
+    for (int e = threadIdx.x; e < kMaxN * kResSlots; e += blockDim.x)
+      pb.sc->res_slots[e / kResSlots][e % kResSlots] = 0ull;
 }
 
 // X = sum_n alpha_n Z_n / sum_n alpha_n (output of Algorithm 1) and E = T - D.
@@ -236,13 +322,41 @@ static int elem_grid(int64_t work) {
   return (int)b;
 }
 
+template <typename S, int NN, int VEC, int RP>
+static void fused_idx(const Problem<S>& p, const RowGeom& rg, hipStream_t s) {
+  const int grid = elem_grid(p.numel / VEC);
+  if (p.numel < (int64_t(1) << 31))
+    hipLaunchKernelGGL((k_fused<S, NN, VEC, RP, uint32_t>), dim3(grid), dim3(256), 0, s, p, rg);
+  else  // tensors of 2^31 elements or more: 64-bit indexing, full rank tile
+    hipLaunchKernelGGL((k_fused<S, NN, VEC, kRT, uint64_t>), dim3(grid), dim3(256), 0, s, p, rg);
+}
+
+template <typename S, int NN, int VEC>
+static void fused_rank(const Problem<S>& p, const RowGeom& rg, hipStream_t s) {
+  int rmax = 1;
+  for (int n = 0; n < p.N; ++n) rmax = p.g[n].R > rmax ? p.g[n].R : rmax;
+  if (rmax <= 4)
+    fused_idx<S, NN, VEC, 4>(p, rg, s);
+  else if (rmax <= 8)
+    fused_idx<S, NN, VEC, 8>(p, rg, s);
+  else if (rmax <= 12)
+    fused_idx<S, NN, VEC, 12>(p, rg, s);
+  else
+    fused_idx<S, NN, VEC, 16>(p, rg, s);
+}
+
 template <typename S, int NN>
 static void fused_n(const Problem<S>& p, hipStream_t s) {
-  const bool vec = (p.g[p.N - 1].I % 4) == 0;
+  RowGeom rg;
+  const int64_t IN = p.g[p.N - 1].I;
+  const bool vec = (IN % 4) == 0;
+  rg.IN = (uint64_t)IN;
+  rg.Q = (uint64_t)(vec ? IN / 4 : IN);
+  for (int n = 0; n < kMaxN; ++n) rg.Rb[n] = n < p.N - 1 ? (uint64_t)(p.g[n].B / IN) : 1;
   if (vec)
-    hipLaunchKernelGGL((k_fused<S, NN, 4>), dim3(elem_grid(p.numel / 4)), dim3(256), 0, s, p);
+    fused_rank<S, NN, 4>(p, rg, s);
   else
-    hipLaunchKernelGGL((k_fused<S, NN, 1>), dim3(elem_grid(p.numel)), dim3(256), 0, s, p);
+    fused_rank<S, NN, 1>(p, rg, s);
 }
 
 template <typename S>
@@ -260,7 +374,7 @@ void launch_fused(const Problem<S>& p, hipStream_t s) {
 
 template <typename S>
 void launch_control(const Problem<S>& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_control<S>, dim3(1), dim3(1), 0, s, p);
+  hipLaunchKernelGGL(k_control<S>, dim3(1), dim3(64), 0, s, p);
 }
 
 template <typename S>

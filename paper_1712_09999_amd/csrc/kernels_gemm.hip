@@ -344,18 +344,32 @@ __global__ void __launch_bounds__(512) k_gemm_m(Problem<S> pb, GroupIdx gi) {
 }
 
 // Fixed-order reduction of the GEMM-M partials: M[i][r] = sum_blk Mpart[blk][i][r].
+// A block owns 64 consecutive entries; its 4 thread groups sum interleaved
+// partials with independent loads in flight, then combine in a fixed order.
 template <typename S>
 __global__ void __launch_bounds__(256) k_reduce_m(Problem<S> pb, GroupIdx gi) {
   if (pb.sc->done || pb.sc->k == 0) return;
   const int n = find_mode(gi, pb.N, blockIdx.x);
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
-  const int64_t e = (int64_t)(blockIdx.x - gi.start[n]) * 256 + threadIdx.x;
+  const int grp = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t e = (int64_t)(blockIdx.x - gi.start[n]) * 64 + l;
   const int64_t ne = (int64_t)g.I * kRT;
-  if (e >= ne) return;
-  double s = 0;
-  for (int b = 0; b < mb.mblocks; ++b) s += mb.Mpart[(int64_t)b * ne + e];
-  mb.M[e] = s;
+  __shared__ double part[4][64];
+  double acc[4] = {0, 0, 0, 0};
+  if (e < ne) {
+    const double* src = mb.Mpart + e;
+    const int nb = mb.mblocks;
+    int b = grp;
+    for (; b + 12 < nb; b += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += src[(int64_t)(b + 4 * u) * ne];
+    }
+    for (; b < nb; b += 4) acc[0] += src[(int64_t)b * ne];
+  }
+  part[grp][l] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (grp == 0 && e < ne) mb.M[e] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +438,7 @@ int gemm_m_blocks(const ModeGeom& g) {
 
 int gram_blocks(const ModeGeom& g) {
   const int64_t steps = (g.J + 15) / 16;
-  int64_t want = 64;
+  int64_t want = 16;
   int64_t maxb = (steps + 3) / 4;
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }
@@ -460,7 +474,7 @@ void launch_reduce_m(const Problem<S>& p, hipStream_t s) {
   int tot = 0;
   for (int n = 0; n < p.N; ++n) {
     gi.start[n] = tot;
-    tot += (int)(((int64_t)p.g[n].I * kRT + 255) / 256);
+    tot += (int)(((int64_t)p.g[n].I * kRT + 63) / 64);
   }
   gi.start[p.N] = tot;
   hipLaunchKernelGGL(k_reduce_m<S>, dim3(tot), dim3(256), 0, s, p, gi);

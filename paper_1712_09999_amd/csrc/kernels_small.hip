@@ -130,52 +130,81 @@ __global__ void __launch_bounds__(64) k_qr(Problem<S> pb) {
 }
 
 // ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi on the R x R Gram (R <= 16), round-robin pairing:
-// every round rotates R'/2 disjoint pairs (R' = R rounded up to even, a dummy
-// index for odd R).  One lane per 2x2 block applies J_k^T S J_l.
+// SVT factor by a warm-started parallel cyclic Jacobi on the R x R Gram.
+//  1. S = sum of the Gram partials (all 256 threads, independent loads);
+//  2. S' = W0^T S W0 with W0 the eigenvectors of the previous iteration
+//     (identity at k = 0), so that S' is nearly diagonal once the iteration
+//     settles; the eigenvectors are accumulated as W = W0 J_1 J_2 ...;
+//  3. round-robin Jacobi: every round rotates R'/2 disjoint pairs (R' = R
+//     rounded up to even, a dummy index for odd R), one lane per 2x2 block;
+//  4. W_f = W diag(f) W^T, U W_f from U staged in LDS.
+// W_f is a spectral function of S, so it does not depend on W0 beyond rounding.
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ void __launch_bounds__(64) k_eig(Problem<S> pb) {
+__global__ void __launch_bounds__(256) k_eig(Problem<S> pb) {
   if (pb.sc->done) return;
   const int n = blockIdx.x;
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
-  const int R = g.R, lane = threadIdx.x;
+  const int R = g.R, I = g.I, tid = threadIdx.x;
+  const bool warm = pb.sc->k > 0;
   __shared__ double Sm[kRT][kRT + 1];
   __shared__ double W[kRT][kRT + 1];
+  __shared__ double T1[kRT][kRT + 1];
   __shared__ double cs[kRT / 2][2];
   __shared__ int pq[kRT / 2][2];
   __shared__ double fac[kRT];
-  __shared__ double Wf[kRT][kRT + 1];
-  for (int e = lane; e < kRT * kRT; e += 64) {
-    const int r = e / kRT, c = e - r * kRT;
-    double s = 0;
-    if (r < R && c < R)
-      for (int b = 0; b < mb.sblocks; ++b) s += mb.Spart[(int64_t)b * kRT * kRT + e];
-    Sm[r][c] = s;
-    W[r][c] = (r == c) ? 1.0 : 0.0;
+  __shared__ double Ul[kQrLds];
+  {
+    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (r < R && c < R) {
+      const double* sp = mb.Spart + tid;
+      const int nb = mb.sblocks;
+      int b = 0;
+      for (; b + 8 <= nb; b += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += sp[(int64_t)(b + u) * kRT * kRT];
+      }
+      for (; b < nb; ++b) acc[0] += sp[(int64_t)b * kRT * kRT];
+    }
+    Sm[r][c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    W[r][c] = (warm && r < R && c < R) ? mb.Wev[tid] : (r == c ? 1.0 : 0.0);
   }
-  // symmetrise (the two triangles are summed in the same order, but be exact)
+  for (int e = tid; e < I * R; e += 256) Ul[e] = mb.U[e];
   __syncthreads();
-  for (int e = lane; e < kRT * kRT; e += 64) {
-    const int r = e / kRT, c = e - r * kRT;
-    if (r > c) Sm[r][c] = Sm[c][r];
+  {  // T1 = S W0 (upper triangle of S mirrored), then S' = W0^T T1, upper triangle mirrored
+    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
+    double t = 0;
+    for (int k = 0; k < R; ++k) t += (r <= k ? Sm[r][k] : Sm[k][r]) * W[k][c];
+    T1[r][c] = t;
+  }
+  __syncthreads();
+  {
+    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
+    double t = 0;
+    const int rr = r <= c ? r : c, cc = r <= c ? c : r;
+    for (int k = 0; k < R; ++k) t += W[k][rr] * T1[k][cc];
+    __syncthreads();
+    Sm[r][c] = (r < R && c < R) ? t : 0.0;
   }
   __syncthreads();
   const int Rp = R + (R & 1);
   const int half = Rp / 2;
   const int m = Rp - 1;
+  int sweeps = 0;
   for (int sweep = 0; sweep < 40 && Rp > 1; ++sweep) {
     int rotated = 0;
+    sweeps = sweep + 1;
     for (int rd = 0; rd < m; ++rd) {
-      if (lane < half) {
+      if (tid < half) {
         int p, q;
-        if (lane == 0) {
+        if (tid == 0) {
           p = m;
           q = rd;
         } else {
-          p = (rd + lane) % m;
-          q = (rd - lane + m) % m;
+          p = (rd + tid) % m;
+          q = (rd - tid + m) % m;
         }
         if (p > q) {
           const int tmp = p;
@@ -194,14 +223,14 @@ __global__ void __launch_bounds__(64) k_eig(Problem<S> pb) {
             rotated = 1;
           }
         }
-        cs[lane][0] = c;
-        cs[lane][1] = s;
-        pq[lane][0] = p;
-        pq[lane][1] = q;
+        cs[tid][0] = c;
+        cs[tid][1] = s;
+        pq[tid][0] = p;
+        pq[tid][1] = q;
       }
       rotated = __syncthreads_or(rotated);
-      if (lane < half * half && lane / half <= lane % half) {
-        const int k = lane / half, l = lane - k * half;
+      if (tid < half * half && tid / half <= tid % half) {
+        const int k = tid / half, l = tid - k * half;
         const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
         const double ck = cs[k][0], sk = cs[k][1], cl = cs[l][0], sl = cs[l][1];
         const double x00 = Sm[pk][pl], x01 = Sm[pk][ql], x10 = Sm[qk][pl], x11 = Sm[qk][ql];
@@ -230,8 +259,8 @@ __global__ void __launch_bounds__(64) k_eig(Problem<S> pb) {
         Sm[pl][qk] = z10;
         Sm[ql][qk] = z11;
       }
-      for (int e = lane; e < kRT * half; e += 64) {
-        const int i = e / half, l = e - i * half;
+      if (tid < kRT * half) {
+        const int i = tid / half, l = tid - (tid / half) * half;
         const int pl = pq[l][0], ql = pq[l][1];
         const double cl = cs[l][0], sl = cs[l][1];
         const double wp = W[i][pl], wq = W[i][ql];
@@ -242,51 +271,350 @@ __global__ void __launch_bounds__(64) k_eig(Problem<S> pb) {
     }
     if (!rotated) break;
   }
+  if (tid == 0) pb.sc->eig_sweeps[n] = sweeps;
   const double tau = pb.lam[n] / pb.sc->mu;
-  if (lane < kRT) {
+  if (tid < kRT) {
     double f = 0.0;
-    if (lane < R) {
-      const double l = Sm[lane][lane];
+    if (tid < R) {
+      const double l = Sm[tid][tid];
       const double sig = sqrt(l > 0.0 ? l : 0.0);
       f = sig > tau ? (sig - tau) / sig : 0.0;
     }
-    fac[lane] = f;
+    fac[tid] = f;
   }
   __syncthreads();
-  {
-    int cnt = (lane < R && fac[lane] > 0.0) ? 1 : 0;
+  if (tid < 64) {
+    int cnt = (tid < R && fac[tid] > 0.0) ? 1 : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if (lane == 0) pb.sc->rank[n] = cnt;
+    if (tid == 0) pb.sc->rank[n] = cnt;
   }
-  for (int e = lane; e < kRT * kRT; e += 64) {
-    const int r = e / kRT, c = e - r * kRT;
+  {
+    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
     double s = 0.0;
     if (r < R && c < R)
       for (int i = 0; i < R; ++i) s += W[r][i] * fac[i] * W[c][i];
-    Wf[r][c] = s;
-    mb.Wf[e] = s;
+    T1[r][c] = s;
+    mb.Wf[tid] = s;
+    mb.Wev[tid] = (r < R && c < R) ? W[r][c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int I = g.I;
-  for (int e = lane; e < I * kRT; e += 64) {
-    const int i = e / kRT, c = e - i * kRT;
+  for (int e = tid; e < I * kRT; e += 256) {
+    const int i = e / kRT, c = e - (e / kRT) * kRT;
     double s = 0.0;
     if (c < R)
-      for (int r = 0; r < R; ++r) s += mb.U[(int64_t)i * R + r] * Wf[r][c];
+      for (int r = 0; r < R; ++r) s += Ul[i * R + r] * T1[r][c];
     mb.Uf[e] = (S)s;
     mb.UfT[(int64_t)c * I + i] = (S)s;
   }
 }
 
+// ---------------------------------------------------------------------------
+// Householder QR with the I x R matrix held in registers of one wave: lane l
+// owns rows l, l + 64, ..., the column loop is unrolled to RP (R <= RP) so
+// every register index is static, and the dot products of one column step
+// are reduced together across the wave.
+// ---------------------------------------------------------------------------
+// Sums K <= 16 values over the 64 lanes of a one-wave block and broadcasts
+// the K sums together with K values `row` of lane `src` to every lane.  Lane
+// (k, c) = (lane % 16, lane / 16) adds rows 16c..16c+15 of column k from LDS;
+// two xor-shuffles combine the four quarters.  The order is fixed.
+constexpr int kBatchLds = 64 * 17 + 32;
+template <int K>
+__device__ __forceinline__ void wave_sum_bcast(double (&v)[K], double (&row)[K], int src,
+                                               double* lds) {
+  constexpr int LD = K + 1;
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < K; ++k) lds[lane * LD + k] = v[k];
+  if (lane == src) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[64 * 17 + 16 + k] = row[k];
+  }
+  __syncthreads();
+  const int k = lane & 15, c = lane >> 4;
+  double s = 0;
+  if (k < K) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += lds[(c * 16 + r) * LD + k];
+  }
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  if (lane < K) lds[64 * 17 + lane] = s;
+  __syncthreads();
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    v[kk] = lds[64 * 17 + kk];
+    row[kk] = lds[64 * 17 + 16 + kk];
+  }
+  __syncthreads();
+}
+
+// One Householder step on column C (compile-time, so every register index is
+// static): with d_j = sum_{i > C} a_iC a_ij for j >= C (d_C is the squared norm
+// below the diagonal), the reflector v = (1, a_{i>C,C} / (alpha - beta)) gives
+// w_j = v^T a_j = a_Cj + d_j / (alpha - beta); one batched reduction per column.
+template <int C, int TR, int RP>
+__device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)[RP], int R,
+                                              int lane, double* lds) {
+  if constexpr (C < RP) {
+    if (C < R) {
+      constexpr int K = RP - C;
+      double d[K], row[K];
+#pragma unroll
+      for (int jj = 0; jj < K; ++jj) {
+        double s = 0;
+#pragma unroll
+        for (int t = 0; t < TR; ++t)
+          if (lane + 64 * t > C) s += a[t][C] * a[t][C + jj];
+        d[jj] = s;
+        row[jj] = a[0][C + jj];  // row C lives in lane C, slot 0
+      }
+      wave_sum_bcast<K>(d, row, C, lds);
+      const double xnorm2 = d[0];
+      const double alpha = row[0];
+      double tc = 0, beta = alpha, scale = 0;
+      if (xnorm2 > 0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tc = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int i = lane + 64 * t;
+        const double v = i > C ? a[t][C] * scale : (i == C ? 1.0 : 0.0);
+#pragma unroll
+        for (int jj = 1; jj < K; ++jj) a[t][C + jj] -= tc * (row[jj] + scale * d[jj]) * v;
+        if (i > C) a[t][C] = v;
+        if (i == C) a[t][C] = beta;
+      }
+      tau[C] = tc;
+    }
+    qr_factor_col<C + 1, TR, RP>(a, tau, R, lane, lds);
+  }
+}
+
+// Backward accumulation of Q = H_0 ... H_{R-1} [I_R; 0], column C down to 0:
+// w_j = a_Cj + sum_{i > C} v_i a_ij for j > C, then column C becomes H_C e_C.
+template <int C, int TR, int RP>
+__device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&tau)[RP], int R,
+                                            int lane, double* lds) {
+  if constexpr (C >= 0) {
+    if (C < R) {
+      const double tc = tau[C];
+      constexpr int K = RP - C - 1;
+      if constexpr (K > 0) {
+        double d[K], row[K];
+#pragma unroll
+        for (int jj = 0; jj < K; ++jj) {
+          double s = 0;
+#pragma unroll
+          for (int t = 0; t < TR; ++t)
+            if (lane + 64 * t > C) s += a[t][C] * a[t][C + 1 + jj];
+          d[jj] = s;
+          row[jj] = a[0][C + 1 + jj];
+        }
+        wave_sum_bcast<K>(d, row, C, lds);
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+          const int i = lane + 64 * t;
+          const double v = i > C ? a[t][C] : (i == C ? 1.0 : 0.0);
+#pragma unroll
+          for (int jj = 0; jj < K; ++jj) a[t][C + 1 + jj] -= tc * (row[jj] + d[jj]) * v;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int i = lane + 64 * t;
+        a[t][C] = i > C ? -tc * a[t][C] : (i == C ? 1.0 - tc : 0.0);
+      }
+    }
+    qr_form_col<C - 1, TR, RP>(a, tau, R, lane, lds);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR with the I x R matrix held in registers of one wave: lane l
+// owns rows l, l + 64, ..., the column loop is unrolled to RP (R <= RP) so
+// every register index is static, and the dot products of one column step
+// are reduced together across the wave.
+// ---------------------------------------------------------------------------
+// One Householder step on column C (compile-time, so every register index is
+// static): reflect rows >= C of columns > C, store v below the diagonal.
+template <int C, int TR, int RP>
+__device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)[RP], int R,
+                                              int lane) {
+  if constexpr (C < RP) {
+    if (C < R) {
+      double part = 0;
+#pragma unroll
+      for (int t = 0; t < TR; ++t)
+        if (lane + 64 * t > C) part += a[t][C] * a[t][C];
+      const double xnorm2 = wave_sum(part);
+      const double alpha = __shfl(a[0][C], C, 64);
+      double tc = 0, beta = alpha, scale = 0;
+      if (xnorm2 > 0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tc = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      double v[TR];
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int i = lane + 64 * t;
+        v[t] = i > C ? a[t][C] * scale : (i == C ? 1.0 : 0.0);
+      }
+      double w[RP];
+#pragma unroll
+      for (int j = 0; j < RP; ++j) {
+        double s = 0;
+        if (j > C) {
+#pragma unroll
+          for (int t = 0; t < TR; ++t) s += v[t] * a[t][j];
+        }
+        w[j] = s;
+      }
+#pragma unroll
+      for (int j = 0; j < RP; ++j)
+        if (j > C) w[j] = wave_sum(w[j]);
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j)
+          if (j > C) a[t][j] -= tc * w[j] * v[t];
+        const int i = lane + 64 * t;
+        if (i > C) a[t][C] = v[t];
+        if (i == C) a[t][C] = beta;
+      }
+      tau[C] = tc;
+    }
+    qr_factor_col<C + 1, TR, RP>(a, tau, R, lane);
+  }
+}
+
+// Backward accumulation of Q = H_0 ... H_{R-1} [I_R; 0], column C down to 0.
+template <int C, int TR, int RP>
+__device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&tau)[RP], int R,
+                                            int lane) {
+  if constexpr (C >= 0) {
+    if (C < R) {
+      const double tc = tau[C];
+      double v[TR];
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+        const int i = lane + 64 * t;
+        v[t] = i > C ? a[t][C] : (i == C ? 1.0 : 0.0);
+      }
+      double w[RP];
+#pragma unroll
+      for (int j = 0; j < RP; ++j) {
+        double s = 0;
+        if (j > C) {
+#pragma unroll
+          for (int t = 0; t < TR; ++t) s += v[t] * a[t][j];
+        }
+        w[j] = s;
+      }
+#pragma unroll
+      for (int j = 0; j < RP; ++j)
+        if (j > C) w[j] = wave_sum(w[j]);
+#pragma unroll
+      for (int t = 0; t < TR; ++t) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j)
+          if (j > C) a[t][j] -= tc * w[j] * v[t];
+        const int i = lane + 64 * t;
+        a[t][C] = i > C ? -tc * v[t] : (i == C ? 1.0 - tc : 0.0);
+      }
+    }
+    qr_form_col<C - 1, TR, RP>(a, tau, R, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR with the I x R matrix held in registers of one wave: lane l
+// owns rows l, l + 64, ...; columns are padded to RP >= R; the dot products
+// of one column step are reduced together across the wave.
+// ---------------------------------------------------------------------------
+template <typename S, int TR, int RP>
+__global__ void __launch_bounds__(64) k_qr_reg(Problem<S> pb) {
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int n = blockIdx.x;
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int I = g.I, R = g.R, lane = threadIdx.x;
+  double a[TR][RP];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int i = lane + 64 * t;
+#pragma unroll
+    for (int c = 0; c < RP; ++c) a[t][c] = (i < I && c < R) ? mb.M[(int64_t)i * kRT + c] : 0.0;
+  }
+  __shared__ double lds[kBatchLds];
+  double tau[RP];
+#pragma unroll
+  for (int c = 0; c < RP; ++c) tau[c] = 0.0;
+  qr_factor_col<0, TR, RP>(a, tau, R, lane, lds);
+  qr_form_col<RP - 1, TR, RP>(a, tau, R, lane, lds);
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int i = lane + 64 * t;
+    if (i < I) {
+#pragma unroll
+      for (int c = 0; c < RP; ++c)
+        if (c < R) mb.U[(int64_t)i * R + c] = a[t][c];
+#pragma unroll
+      for (int c = 0; c < kRT; ++c) {
+        double v = 0.0;
+        if (c < RP)
+          v = c < R ? a[t][c < RP ? c : 0] : 0.0;
+        mb.Us[(int64_t)i * kRT + c] = (S)v;
+      }
+    }
+  }
+}
+
+template <typename S, int TR>
+static bool qr_reg_rp(const Problem<S>& p, int rmax, hipStream_t s) {
+  if (rmax <= 4) {
+    hipLaunchKernelGGL((k_qr_reg<S, TR, 4>), dim3(p.N), dim3(64), 0, s, p);
+  } else if (rmax <= 8) {
+    if (TR > 8) return false;
+    hipLaunchKernelGGL((k_qr_reg<S, (TR > 8 ? 8 : TR), 8>), dim3(p.N), dim3(64), 0, s, p);
+  } else if (rmax <= 12) {
+    if (TR > 4) return false;
+    hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 12>), dim3(p.N), dim3(64), 0, s, p);
+  } else {
+    if (TR > 4) return false;
+    hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 16>), dim3(p.N), dim3(64), 0, s, p);
+  }
+  return true;
+}
+
 template <typename S>
 void launch_qr(const Problem<S>& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_qr<S>, dim3(p.N), dim3(64), 0, s, p);
+  int imax = 1, rmax = 1;
+  for (int n = 0; n < p.N; ++n) {
+    imax = p.g[n].I > imax ? p.g[n].I : imax;
+    rmax = p.g[n].R > rmax ? p.g[n].R : rmax;
+  }
+  bool done = false;
+  if (imax <= 64)
+    done = qr_reg_rp<S, 1>(p, rmax, s);
+  else if (imax <= 128)
+    done = qr_reg_rp<S, 2>(p, rmax, s);
+  else if (imax <= 256)
+    done = qr_reg_rp<S, 4>(p, rmax, s);
+  else if (imax <= 512)
+    done = qr_reg_rp<S, 8>(p, rmax, s);
+  else if (imax <= 1024)
+    done = qr_reg_rp<S, 16>(p, rmax, s);
+  if (!done) hipLaunchKernelGGL(k_qr<S>, dim3(p.N), dim3(64), 0, s, p);
 }
 
 template <typename S>
 void launch_eig(const Problem<S>& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig<S>, dim3(p.N), dim3(64), 0, s, p);
+  hipLaunchKernelGGL(k_eig<S>, dim3(p.N), dim3(256), 0, s, p);
 }
 
 template void launch_qr<float>(const Problem<float>&, hipStream_t);

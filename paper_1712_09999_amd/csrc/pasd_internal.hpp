@@ -9,7 +9,8 @@
 namespace pasd {
 
 constexpr int kMaxN = PASD_MAX_ORDER;
-constexpr int kRT = 16;  // rank tile: R_n is padded to 16 in the factors and partials
+constexpr int kRT = 16;        // rank tile: R_n is padded to 16 in the factors and partials
+constexpr int kResSlots = 64;  // residual maxima are spread over this many words per mode
 
 // Geometry of the mode-n unfolding of a row-major tensor viewed as (A, I, B):
 // element (a, i, b) sits at a*I*B + i*B + b, column index j = a*B + b.
@@ -25,9 +26,12 @@ struct DevScalars {
   int done;  // 0 running, 1 converged, 2 max_iter, 3 numeric
   int converged;
   int pad;
-  unsigned long long res_bits[kMaxN];  // per-iteration residual maxima (as double bits)
   double residual[kMaxN];              // residuals of the last completed iteration
   int rank[kMaxN];
+  int eig_sweeps[kMaxN];               // Jacobi sweeps of the last eigensolve
+  // per-iteration residual maxima as double bits, block b of the fused pass
+  // updates slot b % kResSlots with atomicMax; the control kernel folds them
+  unsigned long long res_slots[kMaxN][kResSlots];
 };
 
 // Per-mode device pointers (state type S for P and Uf, double for U/M/S).

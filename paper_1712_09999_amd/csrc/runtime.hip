@@ -148,7 +148,7 @@ void make_plan(const pasd_config* c, Plan& p) {
   for (int n = 0; n < N; ++n) {
     const ModeGeom& g = p.geom[n];
     p.off_Y[n] = p.L.add(numel * es);
-    p.off_P[n] = p.L.add((size_t)g.R * g.J * es);
+    p.off_P[n] = p.L.add((size_t)kRT * g.J * es);  // rows >= R stay zero
     p.off_U[n] = p.L.add((size_t)g.I * g.R * 8);
     p.off_Us[n] = p.L.add((size_t)g.I * kRT * es);
     p.off_Uf[n] = p.L.add((size_t)g.I * kRT * es);
@@ -249,6 +249,7 @@ void fill_info(pasd_ctx* ctx, pasd_info* info) {
   for (int n = 0; n < ctx->N; ++n) {
     info->residual[n] = s->residual[n];
     info->rank[n] = s->rank[n];
+    info->eig_sweeps[n] = s->eig_sweeps[n];
   }
   info->bytes_resident = ctx->bytes;
 }
@@ -350,6 +351,13 @@ int pasd_create(const pasd_config* cfg, const void* T, int T_on_device, pasd_ctx
   }
   ctx->bytes = pl.L.total + (size_t)numel * ctx->elem;
   ctx->T = static_cast<char*>(ctx->base) + pl.off_T;
+  // zero the whole state once: the padding rows of P_n and columns of the
+  // factors are read by the unrolled kernels and must stay zero
+  e = hipMemsetAsync(ctx->base, 0, pl.L.total, ctx->stream);
+  if (e != hipSuccess) {
+    pasd_destroy(ctx);
+    return fail(PASD_ERR_HIP, std::string("clearing state: ") + hipGetErrorString(e));
+  }
   if (cfg->precision == PASD_FP64)
     fill_problem<double>(ctx, pl, ctx->pd);
   else
@@ -448,7 +456,8 @@ int pasd_get_result(pasd_ctx* ctx, void* X, void* E, int on_device) {
 int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
   g_last_error.clear();
   if (!ctx || !dst) return fail(PASD_ERR_INVALID_ARG, "ctx or dst is NULL");
-  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_Z || q == PASD_Q_U || q == PASD_Q_P || q == PASD_Q_UF;
+  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_Z || q == PASD_Q_U || q == PASD_Q_P ||
+                        q == PASD_Q_UF || q == PASD_Q_WEV;
   if (per_mode && (index < 0 || index >= ctx->N)) return fail(PASD_ERR_INVALID_ARG, "mode index out of range");
   DeviceGuard guard(ctx->dev);
   const bool f64 = ctx->cfg.precision == PASD_FP64;
@@ -509,6 +518,18 @@ int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
                         on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
       return PASD_OK;
     }
+    case PASD_Q_WEV: {
+      const int R = ctx->geom[index].R;
+      double w[kRT * kRT], out[kRT * kRT];
+      const double* s = f64 ? ctx->pd.m[index].Wev : ctx->pf.m[index].Wev;
+      HIP_TRY(hipMemcpyAsync(w, s, sizeof(w), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      for (int r = 0; r < R; ++r)
+        for (int c = 0; c < R; ++c) out[r * R + c] = w[r * kRT + c];
+      HIP_TRY(hipMemcpy(dst, out, sizeof(double) * R * R,
+                        on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+      return PASD_OK;
+    }
     case PASD_Q_SCALARS: {
       int rc = read_scalars(ctx);
       if (rc != PASD_OK) return rc;
@@ -527,7 +548,7 @@ int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
 int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device) {
   g_last_error.clear();
   if (!ctx || !src) return fail(PASD_ERR_INVALID_ARG, "ctx or src is NULL");
-  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_U || q == PASD_Q_P;
+  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_U || q == PASD_Q_P || q == PASD_Q_WEV;
   if (per_mode && (index < 0 || index >= ctx->N)) return fail(PASD_ERR_INVALID_ARG, "mode index out of range");
   DeviceGuard guard(ctx->dev);
   const bool f64 = ctx->cfg.precision == PASD_FP64;
@@ -584,6 +605,18 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
       HIP_TRY(hipMemcpy(d, src, (size_t)ctx->geom[index].R * ctx->geom[index].J * es, kind));
       return PASD_OK;
     }
+    case PASD_Q_WEV: {
+      const int R = ctx->geom[index].R;
+      double in[kRT * kRT], w[kRT * kRT];
+      HIP_TRY(hipMemcpy(in, src, sizeof(double) * R * R,
+                        on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+      for (int r = 0; r < kRT; ++r)
+        for (int c = 0; c < kRT; ++c)
+          w[r * kRT + c] = (r < R && c < R) ? in[r * R + c] : (r == c ? 1.0 : 0.0);
+      double* d = f64 ? ctx->pd.m[index].Wev : ctx->pf.m[index].Wev;
+      HIP_TRY(hipMemcpy(d, w, sizeof(w), hipMemcpyHostToDevice));
+      return PASD_OK;
+    }
     case PASD_Q_SCALARS: {
       double v[2];
       HIP_TRY(hipMemcpy(v, src, sizeof(v), on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
@@ -596,7 +629,8 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
       s.mu = v[1];
       s.done = s.k >= ctx->cfg.max_iter ? 2 : 0;
       s.converged = 0;
-      for (int n = 0; n < kMaxN; ++n) s.res_bits[n] = 0;
+      for (int n = 0; n < kMaxN; ++n)
+        for (int b = 0; b < kResSlots; ++b) s.res_slots[n][b] = 0;
       DevScalars* dsc = f64 ? ctx->pd.sc : ctx->pf.sc;
       HIP_TRY(hipMemcpy(dsc, &s, sizeof(s), hipMemcpyHostToDevice));
       return PASD_OK;

@@ -32,7 +32,7 @@ ERR_STATE = -6
 FP64, FP32, BF16_GEMM = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16_GEMM}
 
-Q_E, Q_Y, Q_Z, Q_X, Q_U, Q_P, Q_UF, Q_SCALARS, Q_D = range(9)
+Q_E, Q_Y, Q_Z, Q_X, Q_U, Q_P, Q_UF, Q_SCALARS, Q_D, Q_WEV = range(10)
 
 # enum pasd_kernel, in launch order
 KERNELS = ("gemm_m", "reduce_m", "qr", "gemm_p", "gram", "eig", "fused", "control")
@@ -65,6 +65,7 @@ class Info(ctypes.Structure):
         ("residual", ctypes.c_double * MAX_ORDER),
         ("rank", ctypes.c_int * MAX_ORDER),
         ("bytes_resident", ctypes.c_size_t),
+        ("eig_sweeps", ctypes.c_int * MAX_ORDER),
     ]
 
 
@@ -253,14 +254,14 @@ class Solver:
             Q_Z: (self.dims, self.np_dtype), Q_X: (self.dims, self.np_dtype),
             Q_U: ((I, R), np.float64), Q_P: ((R, J), self.np_dtype),
             Q_UF: ((I, R), np.float64), Q_SCALARS: ((2,), np.float64),
-            Q_D: (self.dims, self.np_dtype),
+            Q_D: (self.dims, self.np_dtype), Q_WEV: ((R, R), np.float64),
         }[quantity]
         out = np.empty(shape, dtype=dt)
         _check(lib().pasd_export(self.handle, quantity, index, out.ctypes.data_as(ctypes.c_void_p), 0))
         return out
 
     def import_(self, quantity: int, index: int, value: np.ndarray):
-        dt = np.float64 if quantity in (Q_U, Q_SCALARS) else self.np_dtype
+        dt = np.float64 if quantity in (Q_U, Q_SCALARS, Q_WEV) else self.np_dtype
         v = np.ascontiguousarray(value, dtype=dt)
         _check(lib().pasd_import(self.handle, quantity, index, v.ctypes.data_as(ctypes.c_void_p), 0))
 
@@ -270,6 +271,7 @@ class Solver:
             st[f"Y{n}"] = self.export(Q_Y, n)
             st[f"U{n}"] = self.export(Q_U, n)
             st[f"P{n}"] = self.export(Q_P, n)
+            st[f"W{n}"] = self.export(Q_WEV, n)
         return st
 
     def restore(self, st: dict):
@@ -278,6 +280,7 @@ class Solver:
             self.import_(Q_Y, n, st[f"Y{n}"])
             self.import_(Q_U, n, st[f"U{n}"])
             self.import_(Q_P, n, st[f"P{n}"])
+            self.import_(Q_WEV, n, st[f"W{n}"])
         self.import_(Q_SCALARS, 0, st["scalars"])
 
 

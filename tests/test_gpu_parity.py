@@ -129,6 +129,8 @@ SHAPES = [
     ((6, 5, 4), (6, 5, 4), 0.01, 30),
     ((32, 24, 20), (16, 16, 16), 0.05, 25),
     ((130, 9, 70), (5, 4, 6), 0.002, 40),
+    ((300, 10, 8), (6, 3, 3), 0.01, 25),     # QR in registers with 5 rows per lane
+    ((600, 12, 10), (12, 4, 4), 0.01, 20),   # QR falls back to the LDS kernel
 ]
 
 
