@@ -122,19 +122,37 @@ __global__ void __launch_bounds__(256) k_gemm_p(Problem<S> pb, GroupIdx gi) {
     Acc acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = Acc{0, 0, 0, 0};
-    for (int i0 = kbeg; i0 < kend; i0 += 4) {
-      const int i = i0 + q;
-      S gv[4] = {0, 0, 0, 0};
-      S u = 0;
-      if (i < kend) {
-        int64_t o[4];
+    typedef typename MM<S>::vec_t V;
+    if (contig && (tile + 1) * 64 <= g.J) {
+      // all 64 columns valid: unconditional vector loads (rows past kend are
+      // clamped to a valid row and masked), so unrolled iterations overlap
+      const S* __restrict__ Db = pb.D + off[0];
+      const S* __restrict__ Yb = mb.Y + off[0];
+#pragma unroll 4
+      for (int i0 = kbeg; i0 < kend; i0 += 4) {
+        const bool ok = i0 + q < kend;
+        const int i = ok ? i0 + q : kbeg;
+        const V d = *reinterpret_cast<const V*>(Db + (int64_t)i * g.B);
+        const V y = *reinterpret_cast<const V*>(Yb + (int64_t)i * g.B);
+        const S u = ok ? Us[(int64_t)i * kRT + p] : S(0);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) o[t] = off[t] + (int64_t)i * g.B;
-        load_g4<S>(pb.D, mb.Y, o, contig, nvalid, inv_mu, gv);
-        u = Us[(int64_t)i * kRT + p];
+        for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u, ok ? d[t] + y[t] * inv_mu : S(0), acc[t]);
       }
+    } else {
+      for (int i0 = kbeg; i0 < kend; i0 += 4) {
+        const int i = i0 + q;
+        S gv[4] = {0, 0, 0, 0};
+        S u = 0;
+        if (i < kend) {
+          int64_t o[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u, gv[t], acc[t]);
+          for (int t = 0; t < 4; ++t) o[t] = off[t] + (int64_t)i * g.B;
+          load_g4<S>(pb.D, mb.Y, o, contig, nvalid, inv_mu, gv);
+          u = Us[(int64_t)i * kRT + p];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u, gv[t], acc[t]);
+      }
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -162,20 +180,42 @@ __global__ void __launch_bounds__(256) k_gemm_p(Problem<S> pb, GroupIdx gi) {
     const bool rowok = arow < g.A;
     const bool contig = (g.I % 4) == 0;
     Acc acc = Acc{0, 0, 0, 0};
-    for (int i0 = 0; i0 < g.I; i0 += 16) {
-      const int i = i0 + 4 * q;
-      const int nv = max(0, min(4, g.I - i));
-      S gv[4] = {0, 0, 0, 0};
-      if (rowok && nv > 0) {
-        int64_t o[4];
+    if (contig) {
+      // unconditional vector loads: the row is clamped to a valid one and
+      // masked; chunks past I are clamped to the last chunk and masked
+      typedef typename MM<S>::vec_t V;
+      const int64_t ar = rowok ? arow : g.A - 1;
+      const S* __restrict__ Db = pb.D + ar * g.I;
+      const S* __restrict__ Yb = mb.Y + ar * g.I;
+#pragma unroll 4
+      for (int i0 = 0; i0 < g.I; i0 += 16) {
+        const int iq = i0 + 4 * q;
+        const bool ok = iq < g.I;
+        const int i = ok ? iq : g.I - 4;
+        const V d = *reinterpret_cast<const V*>(Db + i);
+        const V y = *reinterpret_cast<const V*>(Yb + i);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) o[t] = arow * g.I + i + t;
-        load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
+        for (int t = 0; t < 4; ++t) {
+          const S u = ok ? Us[(int64_t)(i + t) * kRT + p] : S(0);
+          acc = MM<S>::mma((ok && rowok) ? d[t] + y[t] * inv_mu : S(0), u, acc);
+        }
       }
+    } else {
+      for (int i0 = 0; i0 < g.I; i0 += 16) {
+        const int i = i0 + 4 * q;
+        const int nv = max(0, min(4, g.I - i));
+        S gv[4] = {0, 0, 0, 0};
+        if (rowok && nv > 0) {
+          int64_t o[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const S u = (t < nv) ? Us[(int64_t)(i + t) * kRT + p] : S(0);
-        acc = MM<S>::mma(gv[t], u, acc);
+          for (int t = 0; t < 4; ++t) o[t] = arow * g.I + i + t;
+          load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const S u = (t < nv) ? Us[(int64_t)(i + t) * kRT + p] : S(0);
+          acc = MM<S>::mma(gv[t], u, acc);
+        }
       }
     }
     // D[m][n = p] = P[r = p][a0 + m], m = row(q, v)
@@ -229,7 +269,33 @@ __global__ void __launch_bounds__(512) k_gemm_m(Problem<S> pb, GroupIdx gi) {
       Acc acc[IBP];
 #pragma unroll
       for (int u = 0; u < IBP; ++u) acc[u] = Acc{0, 0, 0, 0};
-      for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
+      // steps whose 16 columns are all valid, on 4-aligned contiguous columns:
+      // unconditional vector loads (rows past I clamped and masked; P_n has
+      // zero rows up to 16), so that the loads of all row blocks overlap
+      const int64_t full_end = (contig && pvec) ? min(send, g.J / 16) : sbeg;
+      int64_t st = sbeg + wave;
+      for (; st < full_end; st += kMWaves) {
+        const int64_t j4 = st * 16 + 4 * q;
+        const int64_t a = j4 / g.B, b = j4 - a * g.B;
+        const int64_t base = a * (int64_t)g.I * g.B + b;
+        const V pvv = *reinterpret_cast<const V*>(mb.P + (int64_t)p * g.J + j4);
+        V dv[IBP], yv[IBP];
+#pragma unroll
+        for (int u = 0; u < IBP; ++u) {
+          const int i = min((ib0 + u) * 16 + p, g.I - 1);
+          dv[u] = *reinterpret_cast<const V*>(pb.D + base + (int64_t)i * g.B);
+          yv[u] = *reinterpret_cast<const V*>(mb.Y + base + (int64_t)i * g.B);
+        }
+#pragma unroll
+        for (int u = 0; u < IBP; ++u) {
+          if (ib0 + u >= nib) break;
+          const bool ok = (ib0 + u) * 16 + p < g.I;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            acc[u] = MM<S>::mma(ok ? dv[u][t] + yv[u][t] * inv_mu : S(0), pvv[t], acc[u]);
+        }
+      }
+      for (; st < send; st += kMWaves) {
         const int64_t j4 = st * 16 + 4 * q;
         int64_t off[4];
         int nvalid = 0;
@@ -300,24 +366,52 @@ __global__ void __launch_bounds__(512) k_gemm_m(Problem<S> pb, GroupIdx gi) {
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[c][t] = Acc{0, 0, 0, 0};
-      for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
-        const int64_t a = st * 4 + q;
-        const bool aok = a < g.A;
-        const S pv = (aok && p < g.R) ? mb.P[(int64_t)p * g.J + a] : S(0);
+      if (contig) {
+        // unconditional loads: row a clamped to A-1, chunk start clamped to
+        // I-4, both masked (P_n has zero rows up to 16)
+#pragma unroll 2
+        for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
+          const int64_t a = st * 4 + q;
+          const bool aok = a < g.A;
+          const int64_t ac = aok ? a : g.A - 1;
+          const S pv0 = mb.P[(int64_t)p * g.J + ac];
+          const S pv = aok ? pv0 : S(0);
+          V dv[4], yv[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          if (c >= CHP || c0 + c >= nch) break;
-          const int i = (c0 + c) * 64 + 4 * p;
-          const int nv = max(0, min(4, g.I - i));
-          S gv[4] = {0, 0, 0, 0};
-          if (aok && nv > 0) {
-            int64_t o[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) o[t] = a * g.I + i + t;
-            load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
+          for (int c = 0; c < 4; ++c) {
+            const int i = min((c0 + c) * 64 + 4 * p, g.I - 4);
+            dv[c] = *reinterpret_cast<const V*>(pb.D + ac * g.I + i);
+            yv[c] = *reinterpret_cast<const V*>(mb.Y + ac * g.I + i);
           }
 #pragma unroll
-          for (int t = 0; t < 4; ++t) acc[c][t] = MM<S>::mma(gv[t], pv, acc[c][t]);
+          for (int c = 0; c < 4; ++c) {
+            if (c >= CHP || c0 + c >= nch) break;
+            const bool ok = (c0 + c) * 64 + 4 * p < g.I;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[c][t] = MM<S>::mma(ok ? dv[c][t] + yv[c][t] * inv_mu : S(0), pv, acc[c][t]);
+          }
+        }
+      } else {
+        for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
+          const int64_t a = st * 4 + q;
+          const bool aok = a < g.A;
+          const S pv = (aok && p < g.R) ? mb.P[(int64_t)p * g.J + a] : S(0);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (c >= CHP || c0 + c >= nch) break;
+            const int i = (c0 + c) * 64 + 4 * p;
+            const int nv = max(0, min(4, g.I - i));
+            S gv[4] = {0, 0, 0, 0};
+            if (aok && nv > 0) {
+              int64_t o[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) o[t] = a * g.I + i + t;
+              load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[c][t] = MM<S>::mma(gv[t], pv, acc[c][t]);
+          }
         }
       }
       for (int c = 0; c < 4; ++c) {
@@ -393,7 +487,17 @@ __global__ void __launch_bounds__(256) k_gram(Problem<S> pb, GroupIdx gi) {
   const int64_t send = min(nsteps, sbeg + per_blk);
   const bool pvec = (g.J % 4) == 0;
   d4v acc = d4v{0, 0, 0, 0};
-  for (int64_t st = sbeg + wave; st < send; st += 4) {
+  // full 16-column steps: unconditional vector loads of row p (rows R..15 of
+  // P_n are zero), so the unrolled iterations keep several loads in flight
+  const int64_t full_end = pvec ? min(send, g.J / 16) : sbeg;
+  int64_t st = sbeg + wave;
+#pragma unroll 4
+  for (; st < full_end; st += 4) {
+    const V v = *reinterpret_cast<const V*>(mb.P + (int64_t)p * g.J + st * 16 + 4 * q);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc = mma64((double)v[t], (double)v[t], acc);
+  }
+  for (; st < send; st += 4) {
     const int64_t j4 = st * 16 + 4 * q;
     double pv[4] = {0, 0, 0, 0};
     if (p < g.R) {

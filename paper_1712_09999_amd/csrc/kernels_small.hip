@@ -171,6 +171,7 @@ __global__ void __launch_bounds__(256) k_eig(Problem<S> pb) {
     Sm[r][c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     W[r][c] = (warm && r < R && c < R) ? mb.Wev[tid] : (r == c ? 1.0 : 0.0);
   }
+#pragma unroll 8
   for (int e = tid; e < I * R; e += 256) Ul[e] = mb.U[e];
   __syncthreads();
   {  // T1 = S W0 (upper triangle of S mirrored), then S' = W0^T T1, upper triangle mirrored
