@@ -77,6 +77,49 @@ def cpu_baseline(T64, ranks, iters):
                       f"(k = 1..{iters}), {dt:.1f} s"}
 
 
+def serving_bench(count, seq_count):
+    """The serving trace: `count` 3-way requests (dims U{32..256}, Tucker ranks
+    U{3..15}, 5-20% U(-10, 10), FP32, tol 1e-6).  Saturation throughput with
+    everything arriving at once, then Poisson arrivals at 0.8x that rate for
+    p50/p99 latency, and the first `seq_count` requests served one at a time by
+    plain pasd_solve as the baseline."""
+    import torch
+
+    import workloads
+    from workloads.torch_gen import tucker_on_device
+    from paper_1712_09999_amd import serving
+
+    trace = workloads.serving_trace(count=count, qps=1.0)
+    tensors = []
+    for spec in trace:
+        T, _, _ = tucker_on_device(spec["dims"], spec["ranks"], spec["frac"], spec["seed"])
+        tensors.append(T)
+    torch.cuda.synchronize()
+    numel = sum(t.numel() for t in tensors)
+
+    def reqs(scale):
+        return [serving.Request(s["index"], s["arrival"] * scale, tensors[s["index"]], s["ranks"],
+                                tol=1e-6, max_iter=1000) for s in trace]
+
+    srv = serving.Server(precision="fp32", max_slots=64, step_iters=4, keep_results=False)
+    sat = serving.latency_summary(srv.run(reqs(0.0), realtime=False))
+    qps = 0.8 * sat["solves_per_s"]
+    pois = serving.latency_summary(srv.run(reqs(1.0 / qps), realtime=True))
+    seq_reqs = reqs(1.0 / qps)[:seq_count]
+    seq = serving.latency_summary(serving.sequential(seq_reqs))
+    return {
+        "requests": count, "mean_numel": numel / count, "precision": "fp32", "max_slots": 64,
+        "saturation": {"solves_per_s": round(sat["solves_per_s"], 2),
+                       "converged": sat["converged"]},
+        "poisson": {"qps": round(qps, 2), "p50_ms": round(pois["p50_ms"], 2),
+                    "p99_ms": round(pois["p99_ms"], 2),
+                    "solves_per_s": round(pois["solves_per_s"], 2)},
+        "sequential_plain": {"requests": seq_count, "solves_per_s": round(seq["solves_per_s"], 2),
+                             "p50_ms": round(seq["p50_ms"], 2), "p99_ms": round(seq["p99_ms"], 2)},
+        "speedup_vs_sequential": round(sat["solves_per_s"] / seq["solves_per_s"], 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +128,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--srv-requests", type=int, default=512)
+    ap.add_argument("--srv-sequential", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -172,6 +218,9 @@ def main():
         out["solve"]["fp32_vs_fp64_rel_err"] = {"X": ex, "E": ee, "within_1e-5": ex <= 1e-5 and ee <= 1e-5}
         out["solve"]["rse_vs_planted_fp64"] = _rel(res["fp64"]["X"], wl.L)
         out["solves_per_s"] = out["solve"]["fp32"]["solves_per_s"]
+
+    if not args.no_serving:
+        out["serving"] = serving_bench(args.srv_requests, min(args.srv_sequential, args.srv_requests))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(T64, ranks, args.cpu_iters)

@@ -80,7 +80,13 @@ typedef struct {
   int precision;                    /* enum pasd_precision, default PASD_FP64 */
   int device;                       /* HIP device ordinal; -1 = current device */
   void *stream;                     /* hipStream_t for all work; NULL = null stream */
+  int flags;                        /* bitwise OR of enum pasd_flags, default 0 */
 } pasd_config;
+
+enum pasd_flags {
+  PASD_FLAG_NO_GRAPH = 1  /* launch every kernel directly instead of replaying a captured
+                             HIP graph of 16 iterations (same results, bitwise) */
+};
 
 /* Progress and status of a context. */
 typedef struct {
@@ -188,6 +194,10 @@ enum pasd_kernel {
  * launches[kind] (arrays of PASD_NUM_KERNELS; launches may be NULL; both are
  * zeroed first).  Iterations skipped after convergence still count. */
 int pasd_profile(pasd_ctx *ctx, int n_iters, double *ms, int *launches);
+
+/* pasd_query for several contexts with a single synchronisation per stream
+ * (serving loops poll every resident solve after each batched step). */
+int pasd_query_batch(pasd_ctx *const *ctxs, int count, pasd_info *infos);
 
 /* Release everything the context holds.  NULL-safe. */
 void pasd_destroy(pasd_ctx *ctx);

@@ -12,6 +12,8 @@
 // large numbers when |E| >> |T - E|.  Then T - Z_n - E = D - Z_n.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pasd_internal.hpp"
 
 namespace pasd {
@@ -89,7 +91,7 @@ __device__ __forceinline__ S nanmax(S a, S b) {
 // the result does not depend on the order.  NaN propagates (its bit pattern
 // exceeds every finite non-negative double).
 template <int NN, typename S>
-__device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rmax)[NN]) {
+__device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rmax)[NN], int lblk) {
   __shared__ double red[4][NN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -103,7 +105,7 @@ __device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rma
   if (threadIdx.x < NN) {
     const int n = threadIdx.x;
     const double r = nanmax(nanmax(red[0][n], red[1][n]), nanmax(red[2][n], red[3][n]));
-    atomicMax(&sc->res_slots[n][blockIdx.x % kResSlots], (unsigned long long)__double_as_longlong(r));
+    atomicMax(&sc->res_slots[n][lblk % kResSlots], (unsigned long long)__double_as_longlong(r));
   }
 }
 
@@ -111,7 +113,6 @@ __device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rma
 // For a mode n < N-1 the row index splits as row = (a * I_n + i_n) * Rb_n + rb
 // with Rb_n = B_n / I_N, and the unfolding column is j = a * B_n + rb * I_N + i.
 struct RowGeom {
-  uint64_t Q;        // VEC-chunks per row (I_N / VEC)
   uint64_t IN;       // I_N
   uint64_t Rb[kMaxN];
 };
@@ -158,9 +159,13 @@ __device__ __forceinline__ void recon_row(const Problem<S>& pb, const RowGeom& r
   }
 }
 
+// One problem's share of the fused pass: `nblk` blocks of which this is `lblk`.
 template <typename S, int NN, int VEC, int RP, typename IT>
-__global__ void __launch_bounds__(256) k_fused(Problem<S> pb, RowGeom rg) {
-  if (pb.sc->done) return;
+__device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk) {
+  RowGeom rg;
+  rg.IN = (uint64_t)pb.g[NN - 1].I;
+#pragma unroll
+  for (int n = 0; n < NN - 1; ++n) rg.Rb[n] = (uint64_t)pb.g[n].B / rg.IN;
   const double mu_d = pb.sc->mu;
   const S mu = (S)mu_d;
   const S inv_mu = (S)(1.0 / mu_d);
@@ -170,8 +175,8 @@ __global__ void __launch_bounds__(256) k_fused(Problem<S> pb, RowGeom rg) {
 #pragma unroll
   for (int n = 0; n < NN; ++n) rmax[n] = S(0);
   const IT nchunk = (IT)(pb.numel / VEC);
-  const IT Q = (IT)rg.Q;
-  for (IT c = (IT)blockIdx.x * blockDim.x + threadIdx.x; c < nchunk; c += (IT)gridDim.x * blockDim.x) {
+  const IT Q = (IT)(rg.IN / VEC);
+  for (IT c = (IT)lblk * blockDim.x + threadIdx.x; c < nchunk; c += (IT)nblk * blockDim.x) {
     const IT row = c / Q;
     const IT i = (c - row * Q) * VEC;
     const IT x0 = c * VEC;
@@ -205,13 +210,29 @@ __global__ void __launch_bounds__(256) k_fused(Problem<S> pb, RowGeom rg) {
 #pragma unroll
     for (int n = 0; n < NN; ++n) storev<S, VEC>(pb.m[n].Y, x0, y[n]);
   }
-  block_residual_max<NN>(pb.sc, rmax);
+  block_residual_max<NN>(pb.sc, rmax, lblk);
+}
+
+// The fused pass over a batch; each problem takes the vector path when its
+// last dimension is a multiple of 4.
+template <typename S, int NN, int RP, typename IT>
+__global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done) return;
+  const int lblk = blockIdx.x - bt.start[req];
+  const int nblk = bt.start[req + 1] - bt.start[req];
+  if (pb.vec4)
+    fused_body<S, NN, 4, RP, IT>(pb, lblk, nblk);
+  else
+    fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk);
 }
 
 // One wave: fold the residual slots (and clear them for the next iteration),
 // then lane 0 applies Algorithm 1, lines 7-8.
 template <typename S>
-__global__ void __launch_bounds__(64) k_control(Problem<S> pb) {
+__global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
+  const Problem<S>& pb = *bt.p[blockIdx.x];
   DevScalars* sc = pb.sc;
   if (sc->done) return;
   __shared__ double res[kMaxN];
@@ -322,59 +343,55 @@ static int elem_grid(int64_t work) {
   return (int)b;
 }
 
-template <typename S, int NN, int VEC, int RP>
-static void fused_idx(const Problem<S>& p, const RowGeom& rg, hipStream_t s) {
-  const int grid = elem_grid(p.numel / VEC);
-  if (p.numel < (int64_t(1) << 31))
-    hipLaunchKernelGGL((k_fused<S, NN, VEC, RP, uint32_t>), dim3(grid), dim3(256), 0, s, p, rg);
+int fused_blocks(int64_t numel, bool vec4) { return elem_grid(vec4 ? numel / 4 : numel); }
+
+template <typename S, int NN, int RP>
+static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.fused_blocks; });
+  bool big = false;
+  for (int r = 0; r < ls.count; ++r) big = big || ls.host[r]->numel >= (int64_t(1) << 31);
+  if (!big)
+    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t>), dim3(grid), dim3(256), 0, s, b);
   else  // tensors of 2^31 elements or more: 64-bit indexing, full rank tile
-    hipLaunchKernelGGL((k_fused<S, NN, VEC, kRT, uint64_t>), dim3(grid), dim3(256), 0, s, p, rg);
+    hipLaunchKernelGGL((k_fused<S, NN, kRT, uint64_t>), dim3(grid), dim3(256), 0, s, b);
 }
 
-template <typename S, int NN, int VEC>
-static void fused_rank(const Problem<S>& p, const RowGeom& rg, hipStream_t s) {
-  int rmax = 1;
-  for (int n = 0; n < p.N; ++n) rmax = p.g[n].R > rmax ? p.g[n].R : rmax;
-  if (rmax <= 4)
-    fused_idx<S, NN, VEC, 4>(p, rg, s);
-  else if (rmax <= 8)
-    fused_idx<S, NN, VEC, 8>(p, rg, s);
-  else if (rmax <= 12)
-    fused_idx<S, NN, VEC, 12>(p, rg, s);
-  else
-    fused_idx<S, NN, VEC, 16>(p, rg, s);
-}
-
+// The rank loop is unrolled to the largest R_n of the set rounded up to 4.
 template <typename S, int NN>
-static void fused_n(const Problem<S>& p, hipStream_t s) {
-  RowGeom rg;
-  const int64_t IN = p.g[p.N - 1].I;
-  const bool vec = (IN % 4) == 0;
-  rg.IN = (uint64_t)IN;
-  rg.Q = (uint64_t)(vec ? IN / 4 : IN);
-  for (int n = 0; n < kMaxN; ++n) rg.Rb[n] = n < p.N - 1 ? (uint64_t)(p.g[n].B / IN) : 1;
-  if (vec)
-    fused_rank<S, NN, 4>(p, rg, s);
+static void fused_n(const LaunchSet<S>& ls, hipStream_t s) {
+  int rmax = 1;
+  for (int r = 0; r < ls.count; ++r)
+    for (int n = 0; n < ls.host[r]->N; ++n) rmax = std::max(rmax, ls.host[r]->g[n].R);
+  if (rmax <= 4)
+    fused_idx<S, NN, 4>(ls, s);
+  else if (rmax <= 8)
+    fused_idx<S, NN, 8>(ls, s);
+  else if (rmax <= 12)
+    fused_idx<S, NN, 12>(ls, s);
   else
-    fused_rank<S, NN, 1>(p, rg, s);
+    fused_idx<S, NN, 16>(ls, s);
 }
 
+// All problems of a set have the same order N (the batch driver groups them).
 template <typename S>
-void launch_fused(const Problem<S>& p, hipStream_t s) {
-  switch (p.N) {
-    case 2: fused_n<S, 2>(p, s); break;
-    case 3: fused_n<S, 3>(p, s); break;
-    case 4: fused_n<S, 4>(p, s); break;
-    case 5: fused_n<S, 5>(p, s); break;
-    case 6: fused_n<S, 6>(p, s); break;
-    case 7: fused_n<S, 7>(p, s); break;
-    default: fused_n<S, 8>(p, s); break;
+void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
+  switch (ls.host[0]->N) {
+    case 2: fused_n<S, 2>(ls, s); break;
+    case 3: fused_n<S, 3>(ls, s); break;
+    case 4: fused_n<S, 4>(ls, s); break;
+    case 5: fused_n<S, 5>(ls, s); break;
+    case 6: fused_n<S, 6>(ls, s); break;
+    case 7: fused_n<S, 7>(ls, s); break;
+    default: fused_n<S, 8>(ls, s); break;
   }
 }
 
 template <typename S>
-void launch_control(const Problem<S>& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_control<S>, dim3(1), dim3(64), 0, s, p);
+void launch_control(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int grid = make_batch(ls, b, [](const Problem<S>&) { return 1; });
+  hipLaunchKernelGGL(k_control<S>, dim3(grid), dim3(64), 0, s, b);
 }
 
 template <typename S>
@@ -394,8 +411,8 @@ void launch_component(const Problem<S>& p, int n, S* Z, hipStream_t s) {
 }
 
 #define INST(S)                                                              \
-  template void launch_fused<S>(const Problem<S>&, hipStream_t);             \
-  template void launch_control<S>(const Problem<S>&, hipStream_t);           \
+  template void launch_fused<S>(const LaunchSet<S>&, hipStream_t);           \
+  template void launch_control<S>(const LaunchSet<S>&, hipStream_t);         \
   template void launch_init<S>(const Problem<S>&, double, hipStream_t);      \
   template void launch_output<S>(const Problem<S>&, S*, S*, hipStream_t);    \
   template void launch_component<S>(const Problem<S>&, int, S*, hipStream_t);

@@ -70,16 +70,6 @@ __device__ __forceinline__ void load_g4(const S* __restrict__ D, const S* __rest
   }
 }
 
-struct GroupIdx {
-  int start[kMaxN + 1];  // first block of each mode
-};
-
-__device__ __forceinline__ int find_mode(const GroupIdx& gi, int N, int blk) {
-  int n = 0;
-  while (n + 1 < N && blk >= gi.start[n + 1]) ++n;
-  return n;
-}
-
 // ---------------------------------------------------------------------------
 // GEMM-P.  Column scheme (B > 1): one block = 64 unfolding columns, its 4 waves
 // split the I_n contraction; lane (p, q) holds columns j0 + 4p .. +3 of row
@@ -90,11 +80,14 @@ __device__ __forceinline__ int find_mode(const GroupIdx& gi, int N, int blk) {
 // ---------------------------------------------------------------------------
 
 template <typename S>
-__global__ void __launch_bounds__(256) k_gemm_p(Problem<S> pb, GroupIdx gi) {
+__global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done) return;
-  const int n = find_mode(gi, pb.N, blockIdx.x);
-  const int64_t tile = blockIdx.x - gi.start[n];
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_GEMM_P], pb.N, lb);
+  const int64_t tile = lb - pb.kb[KB_GEMM_P][n];
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const S inv_mu = S(1.0 / pb.sc->mu);
@@ -242,12 +235,15 @@ __global__ void __launch_bounds__(256) k_gemm_p(Problem<S> pb, GroupIdx gi) {
 constexpr int kMWaves = 8;
 
 template <typename S>
-__global__ void __launch_bounds__(512) k_gemm_m(Problem<S> pb, GroupIdx gi) {
+__global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
   typedef typename MM<S>::vec_t V;
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done || pb.sc->k == 0) return;
-  const int n = find_mode(gi, pb.N, blockIdx.x);
-  const int blk = blockIdx.x - gi.start[n];
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_GEMM_M], pb.N, lb);
+  const int blk = lb - pb.kb[KB_GEMM_M][n];
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const S inv_mu = S(1.0 / pb.sc->mu);
@@ -441,13 +437,16 @@ __global__ void __launch_bounds__(512) k_gemm_m(Problem<S> pb, GroupIdx gi) {
 // A block owns 64 consecutive entries; its 4 thread groups sum interleaved
 // partials with independent loads in flight, then combine in a fixed order.
 template <typename S>
-__global__ void __launch_bounds__(256) k_reduce_m(Problem<S> pb, GroupIdx gi) {
+__global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done || pb.sc->k == 0) return;
-  const int n = find_mode(gi, pb.N, blockIdx.x);
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_REDUCE_M], pb.N, lb);
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int grp = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t e = (int64_t)(blockIdx.x - gi.start[n]) * 64 + l;
+  const int64_t e = (int64_t)(lb - pb.kb[KB_REDUCE_M][n]) * 64 + l;
   const int64_t ne = (int64_t)g.I * kRT;
   __shared__ double part[4][64];
   double acc[4] = {0, 0, 0, 0};
@@ -471,11 +470,14 @@ __global__ void __launch_bounds__(256) k_reduce_m(Problem<S> pb, GroupIdx gi) {
 // A[m][k] = P[m][col], B[k][n] = P[n][col] are the same register.
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ void __launch_bounds__(256) k_gram(Problem<S> pb, GroupIdx gi) {
+__global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
   typedef typename MM<S>::vec_t V;
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done) return;
-  const int n = find_mode(gi, pb.N, blockIdx.x);
-  const int blk = blockIdx.x - gi.start[n];
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_GRAM], pb.N, lb);
+  const int blk = lb - pb.kb[KB_GRAM][n];
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -547,62 +549,50 @@ int gram_blocks(const ModeGeom& g) {
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }
 
+int gemm_p_blocks(const ModeGeom& g) {
+  return (int)(g.B > 1 ? (g.J + 63) / 64 : (g.A + 63) / 64);
+}
+
+int reduce_m_blocks(const ModeGeom& g) { return (int)(((int64_t)g.I * kRT + 63) / 64); }
+
 template <typename S>
-void launch_gemm_p(const Problem<S>& p, hipStream_t s) {
-  GroupIdx gi;
-  int tot = 0;
-  for (int n = 0; n < p.N; ++n) {
-    gi.start[n] = tot;
-    const ModeGeom& g = p.g[n];
-    tot += (int)((g.B > 1 ? (g.J + 63) / 64 : (g.A + 63) / 64));
-  }
-  gi.start[p.N] = tot;
-  hipLaunchKernelGGL(k_gemm_p<S>, dim3(tot), dim3(256), 0, s, p, gi);
+static int mode_grid(const Problem<S>& p, int kind) { return p.kb[kind][p.N]; }
+
+template <typename S>
+void launch_gemm_p(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_P); });
+  hipLaunchKernelGGL(k_gemm_p<S>, dim3(tot), dim3(256), 0, s, b);
 }
 
 template <typename S>
-void launch_gemm_m(const Problem<S>& p, hipStream_t s) {
-  GroupIdx gi;
-  int tot = 0;
-  for (int n = 0; n < p.N; ++n) {
-    gi.start[n] = tot;
-    tot += p.m[n].mblocks;
-  }
-  gi.start[p.N] = tot;
-  hipLaunchKernelGGL(k_gemm_m<S>, dim3(tot), dim3(64 * kMWaves), 0, s, p, gi);
+void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_M); });
+  hipLaunchKernelGGL(k_gemm_m<S>, dim3(tot), dim3(64 * kMWaves), 0, s, b);
 }
 
 template <typename S>
-void launch_reduce_m(const Problem<S>& p, hipStream_t s) {
-  GroupIdx gi;
-  int tot = 0;
-  for (int n = 0; n < p.N; ++n) {
-    gi.start[n] = tot;
-    tot += (int)(((int64_t)p.g[n].I * kRT + 63) / 64);
-  }
-  gi.start[p.N] = tot;
-  hipLaunchKernelGGL(k_reduce_m<S>, dim3(tot), dim3(256), 0, s, p, gi);
+void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_REDUCE_M); });
+  hipLaunchKernelGGL(k_reduce_m<S>, dim3(tot), dim3(256), 0, s, b);
 }
 
 template <typename S>
-void launch_gram(const Problem<S>& p, hipStream_t s) {
-  GroupIdx gi;
-  int tot = 0;
-  for (int n = 0; n < p.N; ++n) {
-    gi.start[n] = tot;
-    tot += p.m[n].sblocks;
-  }
-  gi.start[p.N] = tot;
-  hipLaunchKernelGGL(k_gram<S>, dim3(tot), dim3(256), 0, s, p, gi);
+void launch_gram(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
+  hipLaunchKernelGGL(k_gram<S>, dim3(tot), dim3(256), 0, s, b);
 }
 
-template void launch_gemm_p<float>(const Problem<float>&, hipStream_t);
-template void launch_gemm_p<double>(const Problem<double>&, hipStream_t);
-template void launch_gemm_m<float>(const Problem<float>&, hipStream_t);
-template void launch_gemm_m<double>(const Problem<double>&, hipStream_t);
-template void launch_reduce_m<float>(const Problem<float>&, hipStream_t);
-template void launch_reduce_m<double>(const Problem<double>&, hipStream_t);
-template void launch_gram<float>(const Problem<float>&, hipStream_t);
-template void launch_gram<double>(const Problem<double>&, hipStream_t);
+#define INST(S)                                                         \
+  template void launch_gemm_p<S>(const LaunchSet<S>&, hipStream_t);     \
+  template void launch_gemm_m<S>(const LaunchSet<S>&, hipStream_t);     \
+  template void launch_reduce_m<S>(const LaunchSet<S>&, hipStream_t);   \
+  template void launch_gram<S>(const LaunchSet<S>&, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
 
 }  // namespace pasd

@@ -24,9 +24,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 template <typename S>
-__global__ void __launch_bounds__(64) k_qr(Problem<S> pb) {
+__global__ void __launch_bounds__(64) k_qr(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done || pb.sc->k == 0) return;
-  const int n = blockIdx.x;
+  const int n = blockIdx.x - bt.start[req];
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int I = g.I, R = g.R, lane = threadIdx.x;
@@ -141,9 +143,11 @@ __global__ void __launch_bounds__(64) k_qr(Problem<S> pb) {
 // W_f is a spectral function of S, so it does not depend on W0 beyond rounding.
 // ---------------------------------------------------------------------------
 template <typename S>
-__global__ void __launch_bounds__(256) k_eig(Problem<S> pb) {
+__global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done) return;
-  const int n = blockIdx.x;
+  const int n = blockIdx.x - bt.start[req];
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int R = g.R, I = g.I, tid = threadIdx.x;
@@ -538,9 +542,11 @@ __device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&
 // of one column step are reduced together across the wave.
 // ---------------------------------------------------------------------------
 template <typename S, int TR, int RP>
-__global__ void __launch_bounds__(64) k_qr_reg(Problem<S> pb) {
+__global__ void __launch_bounds__(64) k_qr_reg(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done || pb.sc->k == 0) return;
-  const int n = blockIdx.x;
+  const int n = blockIdx.x - bt.start[req];
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int I = g.I, R = g.R, lane = threadIdx.x;
@@ -576,51 +582,58 @@ __global__ void __launch_bounds__(64) k_qr_reg(Problem<S> pb) {
 }
 
 template <typename S, int TR>
-static bool qr_reg_rp(const Problem<S>& p, int rmax, hipStream_t s) {
+static bool qr_reg_rp(const Batch<S>& b, int grid, int rmax, hipStream_t s) {
   if (rmax <= 4) {
-    hipLaunchKernelGGL((k_qr_reg<S, TR, 4>), dim3(p.N), dim3(64), 0, s, p);
+    hipLaunchKernelGGL((k_qr_reg<S, TR, 4>), dim3(grid), dim3(64), 0, s, b);
   } else if (rmax <= 8) {
     if (TR > 8) return false;
-    hipLaunchKernelGGL((k_qr_reg<S, (TR > 8 ? 8 : TR), 8>), dim3(p.N), dim3(64), 0, s, p);
+    hipLaunchKernelGGL((k_qr_reg<S, (TR > 8 ? 8 : TR), 8>), dim3(grid), dim3(64), 0, s, b);
   } else if (rmax <= 12) {
     if (TR > 4) return false;
-    hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 12>), dim3(p.N), dim3(64), 0, s, p);
+    hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 12>), dim3(grid), dim3(64), 0, s, b);
   } else {
     if (TR > 4) return false;
-    hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 16>), dim3(p.N), dim3(64), 0, s, p);
+    hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 16>), dim3(grid), dim3(64), 0, s, b);
   }
   return true;
 }
 
+// One wave per (problem, mode); the register variant is sized for the largest
+// I_n and R_n of the set, the LDS variant takes what does not fit.
 template <typename S>
-void launch_qr(const Problem<S>& p, hipStream_t s) {
+void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.N; });
   int imax = 1, rmax = 1;
-  for (int n = 0; n < p.N; ++n) {
-    imax = p.g[n].I > imax ? p.g[n].I : imax;
-    rmax = p.g[n].R > rmax ? p.g[n].R : rmax;
-  }
+  for (int r = 0; r < ls.count; ++r)
+    for (int n = 0; n < ls.host[r]->N; ++n) {
+      imax = ls.host[r]->g[n].I > imax ? ls.host[r]->g[n].I : imax;
+      rmax = ls.host[r]->g[n].R > rmax ? ls.host[r]->g[n].R : rmax;
+    }
   bool done = false;
   if (imax <= 64)
-    done = qr_reg_rp<S, 1>(p, rmax, s);
+    done = qr_reg_rp<S, 1>(b, grid, rmax, s);
   else if (imax <= 128)
-    done = qr_reg_rp<S, 2>(p, rmax, s);
+    done = qr_reg_rp<S, 2>(b, grid, rmax, s);
   else if (imax <= 256)
-    done = qr_reg_rp<S, 4>(p, rmax, s);
+    done = qr_reg_rp<S, 4>(b, grid, rmax, s);
   else if (imax <= 512)
-    done = qr_reg_rp<S, 8>(p, rmax, s);
+    done = qr_reg_rp<S, 8>(b, grid, rmax, s);
   else if (imax <= 1024)
-    done = qr_reg_rp<S, 16>(p, rmax, s);
-  if (!done) hipLaunchKernelGGL(k_qr<S>, dim3(p.N), dim3(64), 0, s, p);
+    done = qr_reg_rp<S, 16>(b, grid, rmax, s);
+  if (!done) hipLaunchKernelGGL(k_qr<S>, dim3(grid), dim3(64), 0, s, b);
 }
 
 template <typename S>
-void launch_eig(const Problem<S>& p, hipStream_t s) {
-  hipLaunchKernelGGL(k_eig<S>, dim3(p.N), dim3(256), 0, s, p);
+void launch_eig(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.N; });
+  hipLaunchKernelGGL(k_eig<S>, dim3(grid), dim3(256), 0, s, b);
 }
 
-template void launch_qr<float>(const Problem<float>&, hipStream_t);
-template void launch_qr<double>(const Problem<double>&, hipStream_t);
-template void launch_eig<float>(const Problem<float>&, hipStream_t);
-template void launch_eig<double>(const Problem<double>&, hipStream_t);
+template void launch_qr<float>(const LaunchSet<float>&, hipStream_t);
+template void launch_qr<double>(const LaunchSet<double>&, hipStream_t);
+template void launch_eig<float>(const LaunchSet<float>&, hipStream_t);
+template void launch_eig<double>(const LaunchSet<double>&, hipStream_t);
 
 }  // namespace pasd

@@ -52,7 +52,11 @@ struct ModeBufs {
   int sblocks;   // number of Gram partial blocks
 };
 
-// Everything a kernel needs about the problem, passed by value.
+// Kernels with a per-mode grid: index into Problem::kb.
+enum ModeKernel { KB_GEMM_M = 0, KB_REDUCE_M, KB_GEMM_P, KB_GRAM, KB_COUNT };
+
+// Everything a kernel needs about one solve.  A device copy lives in the
+// solve's own allocation; kernels reach it through a pointer in Batch.
 template <typename S>
 struct Problem {
   int N;
@@ -68,23 +72,81 @@ struct Problem {
   int max_iter;
   int precision;
   double* hist;  // residual history [max_iter][N]
+  // first block of every mode within this problem's grid, per kernel kind
+  int kb[KB_COUNT][kMaxN + 1];
+  int fused_blocks;  // blocks of the fused pass for this problem
+  int vec4;          // last dimension divisible by 4 (vector path of the fused pass)
 };
 
-// Launchers (each enqueues on `stream`; kernels read sc->done and skip).
-template <typename S> void launch_gemm_m(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_reduce_m(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_qr(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_gemm_p(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_gram(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_eig(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_fused(const Problem<S>& p, hipStream_t s);
-template <typename S> void launch_control(const Problem<S>& p, hipStream_t s);
+// One launch over up to kMaxBatch problems (kernel arguments, ~1.6 KB): block
+// b belongs to problem r with start[r] <= b < start[r + 1].  A single solve
+// is a batch of one; a serving step batches every resident solve.
+constexpr int kMaxBatch = 128;
+template <typename S>
+struct Batch {
+  const Problem<S>* p[kMaxBatch];
+  int start[kMaxBatch + 1];
+  int nreq;
+};
+
+__device__ __forceinline__ int batch_find(const int* start, int nreq, int blk) {
+  int lo = 0, hi = nreq - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blk >= start[mid]) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int mode_of(const int* kb, int N, int lblk) {
+  int n = 0;
+  while (n + 1 < N && lblk >= kb[n + 1]) ++n;
+  return n;
+}
+
+// Host view of a launch: host copies (for grid sizes and template choices)
+// and device copies (what the kernels dereference) of the same problems.
+template <typename S>
+struct LaunchSet {
+  int count = 0;
+  const Problem<S>* host[kMaxBatch];
+  const Problem<S>* dev[kMaxBatch];
+};
+
+// Launchers of one iteration's kernels over a set (each enqueues on `s`;
+// kernels read sc->done of their problem and skip).
+template <typename S> void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_qr(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_gemm_p(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_gram(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_eig(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_fused(const LaunchSet<S>& ls, hipStream_t s);
+template <typename S> void launch_control(const LaunchSet<S>& ls, hipStream_t s);
+// Single-problem utilities.
 template <typename S> void launch_init(const Problem<S>& p, double mu0, hipStream_t s);
 template <typename S> void launch_output(const Problem<S>& p, S* X, S* E, hipStream_t s);
 template <typename S> void launch_component(const Problem<S>& p, int n, S* Z, hipStream_t s);
 
-// Block counts chosen on the host for the split-K kernels.
+// Grid sizes chosen on the host.
 int gemm_m_blocks(const ModeGeom& g);
 int gram_blocks(const ModeGeom& g);
+int gemm_p_blocks(const ModeGeom& g);
+int reduce_m_blocks(const ModeGeom& g);
+int fused_blocks(int64_t numel, bool vec4);
+
+// Fill a Batch from a set, with `blocks(problem)` blocks per problem.
+template <typename S, typename F>
+inline int make_batch(const LaunchSet<S>& ls, Batch<S>& b, F blocks) {
+  int tot = 0;
+  b.nreq = ls.count;
+  for (int r = 0; r < ls.count; ++r) {
+    b.p[r] = ls.dev[r];
+    b.start[r] = tot;
+    tot += blocks(*ls.host[r]);
+  }
+  b.start[ls.count] = tot;
+  return tot;
+}
 
 }  // namespace pasd

@@ -32,7 +32,8 @@ int fail(int code, const std::string& msg) {
                   std::string(#expr) + ": " + hipGetErrorString(e_));                   \
   } while (0)
 
-constexpr int kIterChunk = 16;  // iterations enqueued between convergence checks
+constexpr int kIterChunk = 16;   // iterations enqueued between convergence checks
+constexpr int kGraphIters = 16;  // iterations per captured graph
 
 struct Layout {
   size_t total = 0;
@@ -71,6 +72,11 @@ struct pasd_ctx {
   Problem<double> pd;
   void* T = nullptr;
   void* scratch_out = nullptr;  // numel elements, for host exports
+  // kGraphIters iterations captured once (on cap_stream) and replayed on `stream`
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool graph_disabled = false;
+  void* dev_prob = nullptr;  // device copy of pd / pf, inside `base`
 };
 
 namespace {
@@ -115,7 +121,7 @@ int validate_impl(const pasd_config* c) {
 // Buffer plan shared by pasd_footprint and pasd_create.
 struct Plan {
   Layout L;
-  size_t off_T, off_D, off_sc, off_hist;
+  size_t off_T, off_D, off_sc, off_hist, off_prob;
   size_t off_Y[kMaxN], off_P[kMaxN], off_U[kMaxN], off_Us[kMaxN], off_Uf[kMaxN], off_UfT[kMaxN],
       off_Mpart[kMaxN], off_M[kMaxN], off_Spart[kMaxN], off_Wf[kMaxN], off_Wev[kMaxN];
   ModeGeom geom[kMaxN];
@@ -144,6 +150,7 @@ void make_plan(const pasd_config* c, Plan& p) {
   p.off_T = p.L.add(numel * es);
   p.off_D = p.L.add(numel * es);
   p.off_sc = p.L.add(sizeof(DevScalars));
+  p.off_prob = p.L.add(std::max(sizeof(Problem<float>), sizeof(Problem<double>)));
   p.off_hist = p.L.add(sizeof(double) * (size_t)c->max_iter * N);
   for (int n = 0; n < N; ++n) {
     const ModeGeom& g = p.geom[n];
@@ -195,12 +202,24 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   p.tol = ctx->cfg.tol;
   p.max_iter = ctx->cfg.max_iter;
   p.precision = ctx->cfg.precision;
+  // per-mode block offsets of the mode-grouped kernels, and the fused-pass share
+  for (int n = 0; n <= ctx->N; ++n)
+    for (int k = 0; k < KB_COUNT; ++k) p.kb[k][n] = 0;
+  for (int n = 0; n < ctx->N; ++n) {
+    const ModeGeom& g = p.g[n];
+    p.kb[KB_GEMM_M][n + 1] = p.kb[KB_GEMM_M][n] + p.m[n].mblocks;
+    p.kb[KB_REDUCE_M][n + 1] = p.kb[KB_REDUCE_M][n] + reduce_m_blocks(g);
+    p.kb[KB_GEMM_P][n + 1] = p.kb[KB_GEMM_P][n] + gemm_p_blocks(g);
+    p.kb[KB_GRAM][n + 1] = p.kb[KB_GRAM][n] + p.m[n].sblocks;
+  }
+  p.vec4 = (p.g[ctx->N - 1].I % 4) == 0 ? 1 : 0;
+  p.fused_blocks = fused_blocks(p.numel, p.vec4 != 0);
 }
 
 // Enqueue `count` iterations; with `ev` non-null an event is recorded before
 // the first launch and after every launch (ev[it * PASD_NUM_KERNELS + k + 1]).
 template <typename S>
-void enqueue_iterations(const Problem<S>& p, int count, hipStream_t s, hipEvent_t* ev) {
+void enqueue_iterations(const LaunchSet<S>& p, int count, hipStream_t s, hipEvent_t* ev) {
   if (ev) (void)hipEventRecord(ev[0], s);
   for (int it = 0; it < count; ++it) {
     hipEvent_t* e = ev ? ev + (size_t)it * PASD_NUM_KERNELS + 1 : nullptr;
@@ -223,11 +242,60 @@ void enqueue_iterations(const Problem<S>& p, int count, hipStream_t s, hipEvent_
   }
 }
 
+void enqueue_direct(pasd_ctx* ctx, int count, hipStream_t s, hipEvent_t* ev) {
+  if (ctx->cfg.precision == PASD_FP64) {
+    LaunchSet<double> ls;
+    ls.count = 1;
+    ls.host[0] = &ctx->pd;
+    ls.dev[0] = static_cast<const Problem<double>*>(ctx->dev_prob);
+    enqueue_iterations<double>(ls, count, s, ev);
+  } else {
+    LaunchSet<float> ls;
+    ls.count = 1;
+    ls.host[0] = &ctx->pf;
+    ls.dev[0] = static_cast<const Problem<float>*>(ctx->dev_prob);
+    enqueue_iterations<float>(ls, count, s, ev);
+  }
+}
+
+// Capture kGraphIters iterations into a graph once.  Capture needs a stream
+// other than the legacy null stream, so it runs on a private non-blocking
+// stream; the graph is then launched on the context's stream.  Any failure
+// leaves the context on direct launches.
+void ensure_graph(pasd_ctx* ctx) {
+  if (ctx->graph || ctx->graph_disabled) return;
+  ctx->graph_disabled = true;
+  if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    ctx->cap_stream = nullptr;
+    return;
+  }
+  if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return;
+  enqueue_direct(ctx, kGraphIters, ctx->cap_stream, nullptr);
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(ctx->cap_stream, &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess || !ex) {
+    (void)hipGetLastError();
+    return;
+  }
+  ctx->graph = ex;
+  ctx->graph_disabled = false;
+}
+
 int enqueue(pasd_ctx* ctx, int count, hipEvent_t* ev = nullptr) {
-  if (ctx->cfg.precision == PASD_FP64)
-    enqueue_iterations<double>(ctx->pd, count, ctx->stream, ev);
-  else
-    enqueue_iterations<float>(ctx->pf, count, ctx->stream, ev);
+  if (!ev && count >= kGraphIters && !ctx->graph_disabled) {
+    ensure_graph(ctx);
+    if (ctx->graph) {
+      for (; count >= kGraphIters; count -= kGraphIters)
+        HIP_TRY(hipGraphLaunch(ctx->graph, ctx->stream));
+    }
+  }
+  if (count > 0) enqueue_direct(ctx, count, ctx->stream, ev);
   HIP_TRY(hipGetLastError());
   return PASD_OK;
 }
@@ -321,6 +389,7 @@ int pasd_create(const pasd_config* cfg, const void* T, int T_on_device, pasd_ctx
   }
   ctx->dev = dev;
   ctx->stream = static_cast<hipStream_t>(cfg->stream);
+  ctx->graph_disabled = (cfg->flags & PASD_FLAG_NO_GRAPH) != 0;
   ctx->elem = cfg->precision == PASD_FP64 ? 8 : 4;
   Plan pl;
   make_plan(cfg, pl);
@@ -358,10 +427,19 @@ int pasd_create(const pasd_config* cfg, const void* T, int T_on_device, pasd_ctx
     pasd_destroy(ctx);
     return fail(PASD_ERR_HIP, std::string("clearing state: ") + hipGetErrorString(e));
   }
-  if (cfg->precision == PASD_FP64)
+  ctx->dev_prob = static_cast<char*>(ctx->base) + pl.off_prob;
+  if (cfg->precision == PASD_FP64) {
     fill_problem<double>(ctx, pl, ctx->pd);
-  else
+    e = hipMemcpyAsync(ctx->dev_prob, &ctx->pd, sizeof(ctx->pd), hipMemcpyHostToDevice, ctx->stream);
+  } else {
     fill_problem<float>(ctx, pl, ctx->pf);
+    e = hipMemcpyAsync(ctx->dev_prob, &ctx->pf, sizeof(ctx->pf), hipMemcpyHostToDevice, ctx->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    pasd_destroy(ctx);
+    return fail(PASD_ERR_HIP, std::string("problem upload: ") + hipGetErrorString(e));
+  }
   e = hipMemcpyAsync(ctx->T, T, (size_t)numel * ctx->elem, (hipMemcpyKind)copy_kind(T_on_device),
                      ctx->stream);
   if (e != hipSuccess) {
@@ -648,11 +726,64 @@ int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == ctxs[i]) return fail(PASD_ERR_INVALID_ARG, "context repeated in batch");
     if (ctxs[i]->dev != ctxs[0]->dev) return fail(PASD_ERR_INVALID_ARG, "contexts on different devices");
+    if (ctxs[i]->stream != ctxs[0]->stream)
+      return fail(PASD_ERR_INVALID_ARG, "contexts of a batch must share one stream");
   }
+  if (n_iters < 0) return fail(PASD_ERR_INVALID_ARG, "n_iters must be >= 0");
+  if (count == 0 || n_iters == 0) return PASD_OK;
+  DeviceGuard guard(ctxs[0]->dev);
+  // Group by (precision, order); every group runs the eight kernels of an
+  // iteration as grouped launches over up to kMaxBatch problems.
+  std::vector<char> taken(count, 0);
   for (int i = 0; i < count; ++i) {
-    int rc = pasd_step(ctxs[i], n_iters);
-    if (rc != PASD_OK) return rc;
+    if (taken[i]) continue;
+    const int prec = ctxs[i]->cfg.precision, N = ctxs[i]->N;
+    std::vector<pasd_ctx*> grp;
+    for (int j = i; j < count; ++j)
+      if (!taken[j] && ctxs[j]->cfg.precision == prec && ctxs[j]->N == N) {
+        taken[j] = 1;
+        grp.push_back(ctxs[j]);
+      }
+    for (size_t c0 = 0; c0 < grp.size(); c0 += kMaxBatch) {
+      const int cnt = (int)std::min<size_t>(kMaxBatch, grp.size() - c0);
+      if (prec == PASD_FP64) {
+        LaunchSet<double> ls;
+        ls.count = cnt;
+        for (int r = 0; r < cnt; ++r) {
+          ls.host[r] = &grp[c0 + r]->pd;
+          ls.dev[r] = static_cast<const Problem<double>*>(grp[c0 + r]->dev_prob);
+        }
+        enqueue_iterations<double>(ls, n_iters, ctxs[0]->stream, nullptr);
+      } else {
+        LaunchSet<float> ls;
+        ls.count = cnt;
+        for (int r = 0; r < cnt; ++r) {
+          ls.host[r] = &grp[c0 + r]->pf;
+          ls.dev[r] = static_cast<const Problem<float>*>(grp[c0 + r]->dev_prob);
+        }
+        enqueue_iterations<float>(ls, n_iters, ctxs[0]->stream, nullptr);
+      }
+    }
   }
+  HIP_TRY(hipGetLastError());
+  return PASD_OK;
+}
+
+int pasd_query_batch(pasd_ctx* const* ctxs, int count, pasd_info* infos) {
+  g_last_error.clear();
+  if (count < 0 || (count > 0 && (!ctxs || !infos))) return fail(PASD_ERR_INVALID_ARG, "bad arguments");
+  std::vector<hipStream_t> streams;
+  for (int i = 0; i < count; ++i) {
+    pasd_ctx* ctx = ctxs[i];
+    if (!ctx) return fail(PASD_ERR_INVALID_ARG, "NULL context");
+    DeviceGuard guard(ctx->dev);
+    DevScalars* dsc = ctx->cfg.precision == PASD_FP64 ? ctx->pd.sc : ctx->pf.sc;
+    HIP_TRY(hipMemcpyAsync(ctx->host_sc, dsc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+    if (std::find(streams.begin(), streams.end(), ctx->stream) == streams.end())
+      streams.push_back(ctx->stream);
+  }
+  for (hipStream_t s : streams) HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) fill_info(ctxs[i], &infos[i]);
   return PASD_OK;
 }
 
@@ -702,6 +833,8 @@ void pasd_destroy(pasd_ctx* ctx) {
     if (ctx->base) (void)hipFree(ctx->base);
     if (ctx->scratch_out) (void)hipFree(ctx->scratch_out);
     if (ctx->host_sc) (void)hipHostFree(ctx->host_sc);
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   }
   delete ctx;
 }

@@ -30,6 +30,7 @@ ERR_NUMERIC = -5
 ERR_STATE = -6
 
 FP64, FP32, BF16_GEMM = 0, 1, 2
+FLAG_NO_GRAPH = 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16_GEMM}
 
 Q_E, Q_Y, Q_Z, Q_X, Q_U, Q_P, Q_UF, Q_SCALARS, Q_D, Q_WEV = range(10)
@@ -53,6 +54,7 @@ class Config(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("device", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("flags", ctypes.c_int),
     ]
 
 
@@ -102,6 +104,7 @@ def lib():
             "pasd_step_batch": (ctypes.c_int, [P(vp), ctypes.c_int, ctypes.c_int]),
             "pasd_profile": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_double),
                                             P(ctypes.c_int)]),
+            "pasd_query_batch": (ctypes.c_int, [P(vp), ctypes.c_int, P(Info)]),
             "pasd_destroy": (None, [vp]),
             "pasd_last_error": (ctypes.c_char_p, []),
         }
@@ -126,7 +129,8 @@ def _check(code: int, allow=(OK,)) -> int:
 def make_config(dims: Sequence[int], ranks: Sequence[int], lam: Optional[Sequence[float]] = None,
                 alpha: Optional[Sequence[float]] = None, mu0: float = 1e-4, mu_max: float = 1e10,
                 rho: float = 1.1, tol: float = 1e-5, max_iter: int = 1000,
-                precision="fp64", device: int = -1, stream: int = 0) -> Config:
+                precision="fp64", device: int = -1, stream: int = 0,
+                graphs: bool = True) -> Config:
     c = Config()
     lib().pasd_config_init(ctypes.byref(c))
     c.order = len(dims)
@@ -145,6 +149,7 @@ def make_config(dims: Sequence[int], ranks: Sequence[int], lam: Optional[Sequenc
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     c.device = int(device)
     c.stream = int(stream) if stream else None
+    c.flags = 0 if graphs else FLAG_NO_GRAPH
     return c
 
 
@@ -167,7 +172,8 @@ class Solver:
 
     def __init__(self, T, ranks: Sequence[int], *, lam=None, alpha=None, mu0: float = 1e-4,
                  mu_max: float = 1e10, rho: float = 1.1, tol: float = 1e-5, max_iter: int = 1000,
-                 precision="fp64", device: Optional[int] = None, stream: int = 0):
+                 precision="fp64", device: Optional[int] = None, stream: int = 0,
+                 graphs: bool = True):
         import torch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         sdt = torch.float64 if self.precision == FP64 else torch.float32
@@ -183,7 +189,7 @@ class Solver:
         self.torch_dtype = sdt
         self.np_dtype = _state_dtype(self.precision)
         self.cfg = make_config(self.dims, ranks, lam, alpha, mu0, mu_max, rho, tol, max_iter,
-                               self.precision, self.device, stream)
+                               self.precision, self.device, stream, graphs)
         h = ctypes.c_void_p()
         torch.cuda.synchronize(T.device)
         _check(lib().pasd_create(ctypes.byref(self.cfg), ctypes.c_void_p(T.data_ptr()), 1,
@@ -285,5 +291,14 @@ class Solver:
 
 
 def step_batch(solvers: List[Solver], n_iters: int):
+    """n_iters iterations of every solver as grouped launches (pasd_step_batch)."""
     arr = (ctypes.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
     _check(lib().pasd_step_batch(arr, len(solvers), int(n_iters)))
+
+
+def query_batch(solvers: List[Solver]) -> List[Info]:
+    """Progress of several solvers with one synchronisation (pasd_query_batch)."""
+    arr = (ctypes.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
+    infos = (Info * len(solvers))()
+    _check(lib().pasd_query_batch(arr, len(solvers), infos))
+    return list(infos)

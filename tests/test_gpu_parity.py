@@ -165,6 +165,20 @@ def test_c2_full_size_short_schedule(precision):
     _compare(st, s, precision, f"c2/{precision} k=6")
 
 
+@pytest.mark.parametrize("name,mu0", [("c3", 0.1), ("c4", 1.0)])
+def test_full_size_video_and_four_way(name, mu0):
+    """144 x 176 x 400 video-shaped (R = (8, 8, 3)) and 64^4 (R = 6) in FP32,
+    with an initial penalty large enough for the SVT to act within 6 steps."""
+    wl = workloads.make_config(name)
+    T = wl.observed(np.float32).astype(np.float64)
+    st = pasd_init(T, wl.ranks, mu0=mu0)
+    pasd_iterate(st, 6)
+    assert min(st.rank) > 0
+    s = _gpu(T, wl.ranks, "fp32", mu0=mu0)
+    s.step(6)
+    _compare(st, s, "fp32", f"{name}/fp32 k=6")
+
+
 # --------------------------------------------------------------------------- runtime behaviour
 
 def test_checkpoint_restore_is_bitwise():
@@ -190,6 +204,21 @@ def test_runs_are_bitwise_reproducible():
         outs.append((s.export(P.Q_X), s.export(P.Q_E), s.export(P.Q_Y, 1)))
     for a, b in zip(*outs):
         np.testing.assert_array_equal(a, b)
+
+
+def test_graph_replays_match_direct_launches():
+    """Iterations replayed from the captured HIP graph (several replays, with
+    eager work and synchronisation in between) equal direct launches bitwise."""
+    wl = workloads.make_config("c1")
+    a = _gpu(wl.T, wl.ranks, "fp64", graphs=True)
+    b = _gpu(wl.T, wl.ranks, "fp64", graphs=False)
+    for chunk in (16, 32, 16, 48):
+        a.step(chunk)
+        b.step(chunk)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(a.export(P.Q_D), b.export(P.Q_D))
+        np.testing.assert_array_equal(a.export(P.Q_Y, 2), b.export(P.Q_Y, 2))
+    assert a.query().iterations == b.query().iterations == 112
 
 
 def test_reset_restarts_from_initialisation():

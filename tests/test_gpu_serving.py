@@ -1,0 +1,136 @@
+"""Batched stepping and the serving loop on the GPU.
+
+A solve stepped inside a batch (grouped launches over several problems of
+different shapes and ranks) must give the same iterates as the same solve
+stepped alone -- bitwise, since every problem keeps its own data, block
+decomposition and reduction order -- and served results must match the FP64
+oracle within the FP32 bar.
+"""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pasd_init, pasd_iterate, pasd_output
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+from paper_1712_09999_amd import pasd as P  # noqa: E402
+from paper_1712_09999_amd import serving  # noqa: E402
+
+SPECS = [  # (dims, ranks, seed) -- ragged, different ranks and last dims
+    ((40, 36, 32), (4, 3, 5), 11),
+    ((50, 30, 44), (6, 6, 2), 12),
+    ((24, 28, 21), (3, 2, 3), 13),
+    ((64, 20, 36), (8, 5, 7), 14),
+]
+
+
+def _wl(dims, ranks, seed):
+    return workloads.tucker_workload("srv", dims, tuple(min(r, 3) for r in ranks), 0.1, seed,
+                                     value_range=(-10, 10), scale="rms", ranks=ranks)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batched_steps_equal_alone(precision):
+    dt = np.float32 if precision == "fp32" else np.float64
+    wls = [_wl(*s) for s in SPECS]
+    alone, mixed = [], []
+    for wl in wls:
+        a = P.Solver(wl.observed(dt), wl.ranks, precision=precision, tol=0.0, max_iter=10 ** 6,
+                     mu0=0.01)
+        a.step(37)
+        alone.append(a)
+        mixed.append(P.Solver(wl.observed(dt), wl.ranks, precision=precision, tol=0.0,
+                              max_iter=10 ** 6, mu0=0.01))
+    for _ in range(5):
+        P.step_batch(mixed, 7)
+    P.step_batch(mixed[:2], 2)   # a sub-batch, then the rest alone
+    for s in mixed[2:]:
+        s.step(2)
+    for a, b in zip(alone, mixed):
+        assert a.query().iterations == b.query().iterations == 37
+        np.testing.assert_array_equal(a.export(P.Q_D), b.export(P.Q_D))
+        for n in range(3):
+            np.testing.assert_array_equal(a.export(P.Q_Y, n), b.export(P.Q_Y, n))
+
+
+def test_batch_groups_mixed_precision_and_order():
+    wl3 = _wl(*SPECS[0])
+    wl4 = workloads.tucker_workload("srv4", (10, 12, 8, 9), (2, 2, 2, 2), 0.1, 21,
+                                    value_range=(-5, 5), scale="rms")
+    mk = lambda wl, prec: P.Solver(wl.observed(np.float64 if prec == "fp64" else np.float32),
+                                   wl.ranks, precision=prec, tol=0.0, max_iter=10 ** 6, mu0=0.02)
+    combos = [(wl3, "fp32"), (wl3, "fp64"), (wl4, "fp32"), (wl4, "fp64")]
+    mixed = [mk(wl, p) for wl, p in combos]
+    P.step_batch(mixed, 25)
+    infos = P.query_batch(mixed)
+    for (wl, p), s, info in zip(combos, mixed, infos):
+        assert info.iterations == 25
+        a = mk(wl, p)
+        a.step(25)
+        np.testing.assert_array_equal(a.export(P.Q_D), s.export(P.Q_D))
+
+
+def test_served_results_match_alone_and_oracle():
+    wls = [_wl(*s) for s in SPECS]
+    reqs = [serving.Request(i, 0.0, torch.from_numpy(wl.observed(np.float32)).cuda(), wl.ranks,
+                            tol=1e-6, max_iter=300) for i, wl in enumerate(wls)]
+    srv = serving.Server(precision="fp32", max_slots=8, step_iters=4)
+    res = srv.run(reqs, realtime=False)
+    assert [r.rid for r in res] == [0, 1, 2, 3]
+    for wl, r in zip(wls, res):
+        s = P.Solver(wl.observed(np.float32), wl.ranks, precision="fp32", tol=1e-6, max_iter=300)
+        info = s.solve()
+        X, E = (t.cpu().numpy() for t in s.result())
+        assert info.iterations == r.iterations
+        np.testing.assert_array_equal(r.X.cpu().numpy(), X)
+        np.testing.assert_array_equal(r.E.cpu().numpy(), E)
+        # oracle on the same FP32 input, same iteration count
+        st = pasd_init(wl.observed(np.float32).astype(np.float64), wl.ranks)
+        pasd_iterate(st, r.iterations)
+        Xo, Eo = pasd_output(st)
+        ex = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+        ee = np.linalg.norm(E - Eo) / np.linalg.norm(Eo)
+        print(f"request {r.rid}: k={r.iterations} X {ex:.2e} E {ee:.2e}", flush=True)
+        assert ex <= 1e-5 and ee <= 1e-5
+
+
+def test_admission_respects_budget_and_slots():
+    wls = [_wl(*s) for s in SPECS] * 2
+    reqs = [serving.Request(i, 0.0, torch.from_numpy(wl.observed(np.float32)).cuda(), wl.ranks,
+                            tol=1e-6, max_iter=200) for i, wl in enumerate(wls)]
+    fps = [P.footprint(P.make_config(wl.dims, wl.ranks, precision="fp32", max_iter=200))
+           for wl in wls]
+    budget = max(fps) + min(fps)  # room for two small or one large solve at a time
+    srv = serving.Server(precision="fp32", max_slots=3, hbm_budget=budget, step_iters=8,
+                         keep_results=False)
+    res = srv.run(reqs, realtime=False)
+    assert len(res) == len(reqs)
+    # at any instant the admitted-but-unfinished solves fit the budget and slots
+    events = sorted([(r.admitted, fps[r.rid], 1) for r in res] +
+                    [(r.completed, -fps[r.rid], -1) for r in res], key=lambda e: (e[0], e[2]))
+    used = live = 0
+    for _, f, d in events:
+        used += f
+        live += d
+        assert used <= budget and live <= 3
+
+
+def test_batch_rejects_bad_lists():
+    wl = _wl(*SPECS[2])
+    s = P.Solver(wl.observed(np.float32), wl.ranks, precision="fp32")
+    with pytest.raises(P.PasdError):
+        P.step_batch([s, s], 1)
+    st = torch.cuda.Stream()
+    t = P.Solver(wl.observed(np.float32), wl.ranks, precision="fp32", stream=st.cuda_stream)
+    with pytest.raises(P.PasdError):
+        P.step_batch([s, t], 1)
