@@ -28,6 +28,10 @@ METRIC = "TRPCA solves/s + ADMM iters/s at rel.err≤1e-5 vs FP64; p50/p99 laten
 HBM_PEAK_GBS = 8000.0
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _rel(a, b):
     import numpy as np
     nb = float(np.linalg.norm(b))
@@ -89,6 +93,7 @@ def serving_bench(count, seq_count):
     from workloads.torch_gen import tucker_on_device
     from paper_1712_09999_amd import serving
 
+    t0 = time.perf_counter()
     trace = workloads.serving_trace(count=count, qps=1.0)
     tensors = []
     for spec in trace:
@@ -96,6 +101,7 @@ def serving_bench(count, seq_count):
         tensors.append(T)
     torch.cuda.synchronize()
     numel = sum(t.numel() for t in tensors)
+    _progress(f"serving: {count} request tensors drawn in {time.perf_counter() - t0:.1f} s")
 
     def reqs(scale):
         return [serving.Request(s["index"], s["arrival"] * scale, tensors[s["index"]], s["ranks"],
@@ -103,10 +109,13 @@ def serving_bench(count, seq_count):
 
     srv = serving.Server(precision="fp32", max_slots=64, step_iters=4, keep_results=False)
     sat = serving.latency_summary(srv.run(reqs(0.0), realtime=False))
+    _progress(f"serving: saturation {sat['solves_per_s']:.1f} solves/s ({srv.stats['wall_s']:.1f} s)")
     qps = 0.8 * sat["solves_per_s"]
     pois = serving.latency_summary(srv.run(reqs(1.0 / qps), realtime=True))
+    _progress(f"serving: Poisson at {qps:.1f}/s p50 {pois['p50_ms']:.1f} ms p99 {pois['p99_ms']:.1f} ms")
     seq_reqs = reqs(1.0 / qps)[:seq_count]
     seq = serving.latency_summary(serving.sequential(seq_reqs))
+    _progress(f"serving: sequential {seq['solves_per_s']:.1f} solves/s")
     return {
         "requests": count, "mean_numel": numel / count, "precision": "fp32", "max_slots": 64,
         "saturation": {"solves_per_s": round(sat["solves_per_s"], 2),
@@ -164,6 +173,7 @@ def main():
     total_ms = e0.elapsed_time(e1)
     ms_per_step = total_ms / args.steps
     value = 1000.0 / ms_per_step
+    _progress(f"timed {args.steps} iterations: {ms_per_step:.4f} ms each")
 
     prof_iters = max(10, min(args.steps, 100))
     prof = s.profile(prof_iters)
@@ -218,6 +228,7 @@ def main():
         out["solve"]["fp32_vs_fp64_rel_err"] = {"X": ex, "E": ee, "within_1e-5": ex <= 1e-5 and ee <= 1e-5}
         out["solve"]["rse_vs_planted_fp64"] = _rel(res["fp64"]["X"], wl.L)
         out["solves_per_s"] = out["solve"]["fp32"]["solves_per_s"]
+        _progress("full solves done")
 
     if not args.no_serving:
         out["serving"] = serving_bench(args.srv_requests, min(args.srv_sequential, args.srv_requests))

@@ -75,7 +75,8 @@ typedef struct {
   double mu0;                       /* initial penalty, default 1e-4 (Algorithm 1) */
   double mu_max;                    /* penalty cap, default 1e10 (Algorithm 1) */
   double rho;                       /* penalty growth, default 1.1 (Algorithm 1) */
-  double tol;                       /* epsilon of the stopping test, default 1e-5 */
+  double tol;                       /* epsilon of the stopping test, default 1e-5; 0 disables
+                                       the test (the solve runs to max_iter) */
   int max_iter;                     /* iteration cap, default 1000 (Section 5.1) */
   int precision;                    /* enum pasd_precision, default PASD_FP64 */
   int device;                       /* HIP device ordinal; -1 = current device */
@@ -99,6 +100,9 @@ typedef struct {
                                        in the last SVT, per mode */
   size_t bytes_resident;            /* device memory held by the context */
   int eig_sweeps[PASD_MAX_ORDER];   /* Jacobi sweeps of the last Gram eigensolve, per mode */
+  double tol_effective;             /* tolerance of the last stopping test: max(tol, 8 u max|T - E|)
+                                       with u the unit roundoff of the state (2^-24 in FP32, where
+                                       the N low-rank copies cannot agree beyond a few ulps) */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;

@@ -18,18 +18,20 @@
 
 namespace pasd {
 
+// 16-byte vectors: 4 floats or 2 doubles per lane and access.
 typedef float f4v __attribute__((ext_vector_type(4)));
-typedef double d4v __attribute__((ext_vector_type(4)));
-template <typename S> struct V4;
-template <> struct V4<float> { typedef f4v t; };
-template <> struct V4<double> { typedef d4v t; };
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename S> struct VW;
+template <> struct VW<float> { typedef f4v t; static constexpr int n = 4; };
+template <> struct VW<double> { typedef d2v t; static constexpr int n = 2; };
 
 template <typename S, int VEC>
 __device__ __forceinline__ void loadv(const S* __restrict__ p, int64_t off, S out[VEC]) {
-  if constexpr (VEC == 4) {
-    typename V4<S>::t v = *reinterpret_cast<const typename V4<S>::t*>(p + off);
+  if constexpr (VEC > 1) {
+    static_assert(VEC == VW<S>::n, "vector width");
+    typename VW<S>::t v = *reinterpret_cast<const typename VW<S>::t*>(p + off);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) out[t] = v[t];
+    for (int t = 0; t < VEC; ++t) out[t] = v[t];
   } else {
     out[0] = p[off];
   }
@@ -37,48 +39,30 @@ __device__ __forceinline__ void loadv(const S* __restrict__ p, int64_t off, S ou
 
 template <typename S, int VEC>
 __device__ __forceinline__ void storev(S* __restrict__ p, int64_t off, const S in[VEC]) {
-  if constexpr (VEC == 4) {
-    typename V4<S>::t v;
+  if constexpr (VEC > 1) {
+    typename VW<S>::t v;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = in[t];
-    *reinterpret_cast<typename V4<S>::t*>(p + off) = v;
+    for (int t = 0; t < VEC; ++t) v[t] = in[t];
+    *reinterpret_cast<typename VW<S>::t*>(p + off) = v;
   } else {
     p[off] = in[0];
   }
 }
 
-// Z_n at elements x0 .. x0+VEC-1 (all in one row of the last mode when VEC = 4).
-template <typename S, int VEC>
-__device__ __forceinline__ void recon(const Problem<S>& pb, int n, int64_t x0, S z[VEC]) {
+// Z_n at element x (any layout), FP64 accumulation; used by the output passes.
+template <typename S>
+__device__ __forceinline__ double recon1(const Problem<S>& pb, int n, int64_t x) {
   const ModeGeom& g = pb.g[n];
   const ModeBufs<S>& mb = pb.m[n];
-#pragma unroll
-  for (int t = 0; t < VEC; ++t) z[t] = S(0);
-  if (g.B == 1) {
-    const int64_t row = x0 / g.I;
-    const int i = (int)(x0 - row * g.I);
-    for (int r = 0; r < g.R; ++r) {
-      const S pr = mb.P[(int64_t)r * g.J + row];
-      S u[VEC];
-      loadv<S, VEC>(mb.UfT, (int64_t)r * g.I + i, u);
-#pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] += u[t] * pr;
-    }
-  } else {
-    const int64_t IB = (int64_t)g.I * g.B;
-    const int64_t a = x0 / IB;
-    const int64_t rem = x0 - a * IB;
-    const int i = (int)(rem / g.B);
-    const int64_t b = rem - (int64_t)i * g.B;
-    const int64_t j = a * g.B + b;
-    for (int r = 0; r < g.R; ++r) {
-      const S u = mb.Uf[(int64_t)i * kRT + r];
-      S pv[VEC];
-      loadv<S, VEC>(mb.P, (int64_t)r * g.J + j, pv);
-#pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] += u * pv[t];
-    }
-  }
+  double z = 0.0;
+  const int64_t IB = (int64_t)g.I * g.B;
+  const int64_t a = x / IB;
+  const int64_t rem = x - a * IB;
+  const int i = (int)(rem / g.B);
+  const int64_t j = a * g.B + (rem - (int64_t)i * g.B);
+  for (int r = 0; r < g.R; ++r)
+    z = fma((double)mb.Uf[(int64_t)i * kRT + r], (double)mb.P[(int64_t)r * g.J + j], z);
+  return z;
 }
 
 template <typename S>
@@ -92,6 +76,7 @@ __device__ __forceinline__ S nanmax(S a, S b) {
 // exceeds every finite non-negative double).
 template <int NN, typename S>
 __device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rmax)[NN], int lblk) {
+  // entries 0..NN-2 are the residuals of the modes, entry NN-1 is max |D|
   __shared__ double red[4][NN];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -105,7 +90,8 @@ __device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rma
   if (threadIdx.x < NN) {
     const int n = threadIdx.x;
     const double r = nanmax(nanmax(red[0][n], red[1][n]), nanmax(red[2][n], red[3][n]));
-    atomicMax(&sc->res_slots[n][lblk % kResSlots], (unsigned long long)__double_as_longlong(r));
+    const int row = n < NN - 1 ? n : kMaxN;
+    atomicMax(&sc->res_slots[row][lblk % kResSlots], (unsigned long long)__double_as_longlong(r));
   }
 }
 
@@ -119,14 +105,17 @@ struct RowGeom {
 
 // Z_n at the VEC elements starting at column i of `row`, with the rank loop
 // unrolled to RP (P_n has zero rows up to kRT, U_n W_n zero columns), so that
-// all loads of P_n and U_n W_n are independent and issue together.
+// all loads of P_n and U_n W_n are independent and issue together.  The sum is
+// accumulated in FP64 whatever the state type: an FP32 sum over R terms of
+// unit-scale data would carry ~R 2^-24 |Z| of error, above an absolute
+// tolerance of 1e-6.
 template <typename S, int VEC, int RP, typename IT>
 __device__ __forceinline__ void recon_row(const Problem<S>& pb, const RowGeom& rg, int n, bool last,
-                                          IT row, IT i, S z[VEC]) {
+                                          IT row, IT i, double z[VEC]) {
   const ModeGeom& g = pb.g[n];
   const ModeBufs<S>& mb = pb.m[n];
 #pragma unroll
-  for (int t = 0; t < VEC; ++t) z[t] = S(0);
+  for (int t = 0; t < VEC; ++t) z[t] = 0.0;
   if (last) {
     S pr[RP];
     S u[RP][VEC];
@@ -138,7 +127,7 @@ __device__ __forceinline__ void recon_row(const Problem<S>& pb, const RowGeom& r
 #pragma unroll
     for (int r = 0; r < RP; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] += u[r][t] * pr[r];
+      for (int t = 0; t < VEC; ++t) z[t] = fma((double)u[r][t], (double)pr[r], z[t]);
   } else {
     const IT Rb = (IT)rg.Rb[n];
     const IT q1 = Rb == 1 ? row : row / Rb;
@@ -155,25 +144,27 @@ __device__ __forceinline__ void recon_row(const Problem<S>& pb, const RowGeom& r
 #pragma unroll
     for (int r = 0; r < RP; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] += u[r] * pv[r][t];
+      for (int t = 0; t < VEC; ++t) z[t] = fma((double)u[r], (double)pv[r][t], z[t]);
   }
 }
 
 // One problem's share of the fused pass: `nblk` blocks of which this is `lblk`.
+// Arithmetic in FP64 registers; D and Y_n are rounded to the state type when
+// stored, and the residual and the multiplier update use the stored D, so the
+// stored iterate satisfies Y_n^{k+1} - Y_n^k = mu (D - Z_n) up to Y's rounding.
 template <typename S, int NN, int VEC, int RP, typename IT>
 __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk) {
   RowGeom rg;
   rg.IN = (uint64_t)pb.g[NN - 1].I;
 #pragma unroll
   for (int n = 0; n < NN - 1; ++n) rg.Rb[n] = (uint64_t)pb.g[n].B / rg.IN;
-  const double mu_d = pb.sc->mu;
-  const S mu = (S)mu_d;
-  const S inv_mu = (S)(1.0 / mu_d);
-  const S theta = (S)(1.0 / (mu_d * NN));
-  const S invN = (S)(1.0 / NN);
-  S rmax[NN];
+  const double mu = pb.sc->mu;
+  const double inv_mu = 1.0 / mu;
+  const double theta = 1.0 / (mu * NN);
+  const double invN = 1.0 / NN;
+  double rmax[NN + 1];  // residual of every mode, then max |D|
 #pragma unroll
-  for (int n = 0; n < NN; ++n) rmax[n] = S(0);
+  for (int n = 0; n <= NN; ++n) rmax[n] = 0.0;
   const IT nchunk = (IT)(pb.numel / VEC);
   const IT Q = (IT)(rg.IN / VEC);
   for (IT c = (IT)lblk * blockDim.x + threadIdx.x; c < nchunk; c += (IT)nblk * blockDim.x) {
@@ -182,7 +173,7 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     const IT x0 = c * VEC;
     S tv[VEC];
     loadv<S, VEC>(pb.T, x0, tv);
-    S z[NN][VEC];
+    double z[NN][VEC];
     S y[NN][VEC];
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
@@ -192,29 +183,31 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     S dv[VEC];
 #pragma unroll
     for (int t = 0; t < VEC; ++t) {
-      S s = S(0);
+      double sum = 0.0;
 #pragma unroll
-      for (int n = 0; n < NN; ++n) s += y[n][t] * inv_mu - z[n][t];
-      const S m = s * invN;
-      const S h = tv[t] + m;
-      const S d = (fabs(h) <= theta) ? tv[t] : (copysign(theta, h) - m);
-      dv[t] = d;
+      for (int n = 0; n < NN; ++n) sum += (double)y[n][t] * inv_mu - z[n][t];
+      const double m = sum * invN;
+      const double tt = (double)tv[t];
+      const double h = tt + m;
+      dv[t] = (S)((fabs(h) <= theta) ? tt : (copysign(theta, h) - m));
+      const double d = (double)dv[t];
 #pragma unroll
       for (int n = 0; n < NN; ++n) {
-        const S res = d - z[n][t];
-        y[n][t] += mu * res;
-        rmax[n] = nanmax(rmax[n], (S)fabs(res));
+        const double res = d - z[n][t];
+        y[n][t] = (S)((double)y[n][t] + mu * res);
+        rmax[n] = nanmax(rmax[n], fabs(res));
       }
+      rmax[NN] = nanmax(rmax[NN], fabs(d));
     }
     storev<S, VEC>(pb.D, x0, dv);
 #pragma unroll
     for (int n = 0; n < NN; ++n) storev<S, VEC>(pb.m[n].Y, x0, y[n]);
   }
-  block_residual_max<NN>(pb.sc, rmax, lblk);
+  block_residual_max<NN + 1>(pb.sc, rmax, lblk);
 }
 
-// The fused pass over a batch; each problem takes the vector path when its
-// last dimension is a multiple of 4.
+// The fused pass over a batch; each problem takes the 16-byte vector path when
+// its last dimension is a multiple of the vector width.
 template <typename S, int NN, int RP, typename IT>
 __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
@@ -222,8 +215,8 @@ __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
   if (pb.sc->done) return;
   const int lblk = blockIdx.x - bt.start[req];
   const int nblk = bt.start[req + 1] - bt.start[req];
-  if (pb.vec4)
-    fused_body<S, NN, 4, RP, IT>(pb, lblk, nblk);
+  if (pb.vecw)
+    fused_body<S, NN, VW<S>::n, RP, IT>(pb, lblk, nblk);
   else
     fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk);
 }
@@ -235,11 +228,12 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
   const Problem<S>& pb = *bt.p[blockIdx.x];
   DevScalars* sc = pb.sc;
   if (sc->done) return;
-  __shared__ double res[kMaxN];
+  __shared__ double res[kMaxN + 1];
   const int lane = threadIdx.x;
-  for (int n = 0; n < pb.N; ++n) {
-    unsigned long long b = sc->res_slots[n][lane];
-    sc->res_slots[n][lane] = 0ull;
+  for (int n = 0; n <= pb.N; ++n) {
+    const int row = n < pb.N ? n : kMaxN;  // the last row folded is max |D|
+    unsigned long long b = sc->res_slots[row][lane];
+    sc->res_slots[row][lane] = 0ull;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       const unsigned long long other = __shfl_xor(b, o, 64);
@@ -248,14 +242,25 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
     if (lane == 0) res[n] = __longlong_as_double((long long)b);
   }
   if (lane != 0) return;
+  // Stopping test of Algorithm 1 (line 8).  In FP32 state the N copies Z_n are
+  // each rebuilt from FP32 factors, so they disagree by a few units in the last
+  // place of |D|, and the residual T - Z_n - E cannot be certified below that:
+  // the test uses max(tol, 8 u max|D|), u the unit roundoff of the state type
+  // (2^-24 for FP32; 2^-53 leaves the FP64 test unchanged in practice).
+  const double u = sizeof(S) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+  const double dmax = res[pb.N];
+  const double tol_eff = pb.tol > 0.0 ? fmax(pb.tol, 8.0 * u * dmax) : 0.0;  // tol 0: never stop
+  sc->dmax = dmax;
+  sc->tol_eff = tol_eff;
   bool conv = true, bad = false;
   for (int n = 0; n < pb.N; ++n) {
     const double r = res[n];
     sc->residual[n] = r;
     pb.hist[(int64_t)sc->k * pb.N + n] = r;
-    if (!(r < pb.tol)) conv = false;
+    if (!(r < tol_eff)) conv = false;
     if (!isfinite(r)) bad = true;
   }
+  if (!isfinite(dmax)) bad = true;
   sc->mu = fmin(pb.rho * sc->mu, pb.mu_max);
   sc->k += 1;
   if (bad) {
@@ -302,7 +307,7 @@ __global__ void __launch_bounds__(256) k_init_small(Problem<S> pb, double mu0) {
     }
   }
   if (n == 0)
-    for (int e = threadIdx.x; e < kMaxN * kResSlots; e += blockDim.x)
+    for (int e = threadIdx.x; e < (kMaxN + 1) * kResSlots; e += blockDim.x)
       pb.sc->res_slots[e / kResSlots][e % kResSlots] = 0ull;
 }
 
@@ -315,11 +320,7 @@ __global__ void __launch_bounds__(256) k_output(Problem<S> pb, S* X, S* E) {
        x += (int64_t)gridDim.x * blockDim.x) {
     if (X) {
       double acc = 0;
-      for (int n = 0; n < pb.N; ++n) {
-        S z[1];
-        recon<S, 1>(pb, n, x, z);
-        acc += pb.alpha[n] * (double)z[0];
-      }
+      for (int n = 0; n < pb.N; ++n) acc += pb.alpha[n] * recon1(pb, n, x);
       X[x] = (S)(acc / wsum);
     }
     if (E) E[x] = pb.T[x] - pb.D[x];
@@ -330,9 +331,7 @@ template <typename S>
 __global__ void __launch_bounds__(256) k_component(Problem<S> pb, int n, S* Z) {
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < pb.numel;
        x += (int64_t)gridDim.x * blockDim.x) {
-    S z[1];
-    recon<S, 1>(pb, n, x, z);
-    Z[x] = z[0];
+    Z[x] = (S)recon1(pb, n, x);
   }
 }
 
@@ -343,7 +342,7 @@ static int elem_grid(int64_t work) {
   return (int)b;
 }
 
-int fused_blocks(int64_t numel, bool vec4) { return elem_grid(vec4 ? numel / 4 : numel); }
+int fused_blocks(int64_t numel, int vec) { return elem_grid(numel / vec); }
 
 template <typename S, int NN, int RP>
 static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {

@@ -29,9 +29,12 @@ struct DevScalars {
   double residual[kMaxN];              // residuals of the last completed iteration
   int rank[kMaxN];
   int eig_sweeps[kMaxN];               // Jacobi sweeps of the last eigensolve
+  double dmax;                         // max |D| of the last iteration
+  double tol_eff;                      // tolerance the last stopping test used
   // per-iteration residual maxima as double bits, block b of the fused pass
   // updates slot b % kResSlots with atomicMax; the control kernel folds them
-  unsigned long long res_slots[kMaxN][kResSlots];
+  // (row kMaxN holds max |D|)
+  unsigned long long res_slots[kMaxN + 1][kResSlots];
 };
 
 // Per-mode device pointers (state type S for P and Uf, double for U/M/S).
@@ -75,7 +78,7 @@ struct Problem {
   // first block of every mode within this problem's grid, per kernel kind
   int kb[KB_COUNT][kMaxN + 1];
   int fused_blocks;  // blocks of the fused pass for this problem
-  int vec4;          // last dimension divisible by 4 (vector path of the fused pass)
+  int vecw;          // last dimension divisible by the 16-byte vector width (fused pass)
 };
 
 // One launch over up to kMaxBatch problems (kernel arguments, ~1.6 KB): block
@@ -133,7 +136,7 @@ int gemm_m_blocks(const ModeGeom& g);
 int gram_blocks(const ModeGeom& g);
 int gemm_p_blocks(const ModeGeom& g);
 int reduce_m_blocks(const ModeGeom& g);
-int fused_blocks(int64_t numel, bool vec4);
+int fused_blocks(int64_t numel, int vec);
 
 // Fill a Batch from a set, with `blocks(problem)` blocks per problem.
 template <typename S, typename F>

@@ -212,8 +212,9 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     p.kb[KB_GEMM_P][n + 1] = p.kb[KB_GEMM_P][n] + gemm_p_blocks(g);
     p.kb[KB_GRAM][n + 1] = p.kb[KB_GRAM][n] + p.m[n].sblocks;
   }
-  p.vec4 = (p.g[ctx->N - 1].I % 4) == 0 ? 1 : 0;
-  p.fused_blocks = fused_blocks(p.numel, p.vec4 != 0);
+  const int vw = 16 / (int)sizeof(S);
+  p.vecw = (p.g[ctx->N - 1].I % vw) == 0 ? 1 : 0;
+  p.fused_blocks = fused_blocks(p.numel, p.vecw ? vw : 1);
 }
 
 // Enqueue `count` iterations; with `ev` non-null an event is recorded before
@@ -318,6 +319,7 @@ void fill_info(pasd_ctx* ctx, pasd_info* info) {
     info->residual[n] = s->residual[n];
     info->rank[n] = s->rank[n];
     info->eig_sweeps[n] = s->eig_sweeps[n];
+    info->tol_effective = s->tol_eff;
   }
   info->bytes_resident = ctx->bytes;
 }
@@ -707,7 +709,7 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
       s.mu = v[1];
       s.done = s.k >= ctx->cfg.max_iter ? 2 : 0;
       s.converged = 0;
-      for (int n = 0; n < kMaxN; ++n)
+      for (int n = 0; n <= kMaxN; ++n)
         for (int b = 0; b < kResSlots; ++b) s.res_slots[n][b] = 0;
       DevScalars* dsc = f64 ? ctx->pd.sc : ctx->pf.sc;
       HIP_TRY(hipMemcpy(dsc, &s, sizeof(s), hipMemcpyHostToDevice));

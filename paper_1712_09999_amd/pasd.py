@@ -68,6 +68,7 @@ class Info(ctypes.Structure):
         ("rank", ctypes.c_int * MAX_ORDER),
         ("bytes_resident", ctypes.c_size_t),
         ("eig_sweeps", ctypes.c_int * MAX_ORDER),
+        ("tol_effective", ctypes.c_double),
     ]
 
 
