@@ -25,30 +25,6 @@ template <typename S> struct VW;
 template <> struct VW<float> { typedef f4v t; static constexpr int n = 4; };
 template <> struct VW<double> { typedef d2v t; static constexpr int n = 2; };
 
-template <typename S, int VEC>
-__device__ __forceinline__ void loadv(const S* __restrict__ p, int64_t off, S out[VEC]) {
-  if constexpr (VEC > 1) {
-    static_assert(VEC == VW<S>::n, "vector width");
-    typename VW<S>::t v = *reinterpret_cast<const typename VW<S>::t*>(p + off);
-#pragma unroll
-    for (int t = 0; t < VEC; ++t) out[t] = v[t];
-  } else {
-    out[0] = p[off];
-  }
-}
-
-template <typename S, int VEC>
-__device__ __forceinline__ void storev(S* __restrict__ p, int64_t off, const S in[VEC]) {
-  if constexpr (VEC > 1) {
-    typename VW<S>::t v;
-#pragma unroll
-    for (int t = 0; t < VEC; ++t) v[t] = in[t];
-    *reinterpret_cast<typename VW<S>::t*>(p + off) = v;
-  } else {
-    p[off] = in[0];
-  }
-}
-
 // Z_n at element x (any layout), FP64 accumulation; used by the output passes.
 template <typename S>
 __device__ __forceinline__ double recon1(const Problem<S>& pb, int n, int64_t x) {
@@ -95,115 +71,217 @@ __device__ __forceinline__ void block_residual_max(DevScalars* sc, const S (&rma
   }
 }
 
-// Row view of the tensor for the fused pass: rows = numel / I_N of length I_N.
-// For a mode n < N-1 the row index splits as row = (a * I_n + i_n) * Rb_n + rb
-// with Rb_n = B_n / I_N, and the unfolding column is j = a * B_n + rb * I_N + i.
-struct RowGeom {
-  uint64_t IN;       // I_N
-  uint64_t Rb[kMaxN];
+// Accesses of the fused pass go through explicitly global pointers (no generic
+// "flat" accesses, which also occupy the LDS/scalar wait counter) at a uniform
+// base plus an element offset.  With a 32-bit index type the byte offset is a
+// 32-bit value (the host takes that path only when every offset of the pass
+// fits in 32 bits); otherwise it is 64-bit.
+#define PASD_GLOBAL __attribute__((address_space(1)))
+
+template <typename S, typename IT>
+__device__ __forceinline__ uint64_t byte_off(IT idx) {
+  if constexpr (sizeof(IT) == 4)
+    return (uint32_t)(idx * (uint32_t)sizeof(S));
+  else
+    return (uint64_t)idx * sizeof(S);
+}
+
+template <typename S, int VEC, typename IT>
+__device__ __forceinline__ void gload(const S* base, IT idx, S out[VEC]) {
+  const PASD_GLOBAL char* p = (const PASD_GLOBAL char*)base + byte_off<S, IT>(idx);
+  if constexpr (VEC > 1) {
+    static_assert(VEC == VW<S>::n, "vector width");
+    const typename VW<S>::t v = *(const PASD_GLOBAL typename VW<S>::t*)p;
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) out[t] = v[t];
+  } else {
+    out[0] = *(const PASD_GLOBAL S*)p;
+  }
+}
+
+template <typename S, int VEC, typename IT>
+__device__ __forceinline__ void gstore(S* base, IT idx, const S in[VEC]) {
+  PASD_GLOBAL char* p = (PASD_GLOBAL char*)base + byte_off<S, IT>(idx);
+  if constexpr (VEC > 1) {
+    typename VW<S>::t v;
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) v[t] = in[t];
+    *(PASD_GLOBAL typename VW<S>::t*)p = v;
+  } else {
+    *(PASD_GLOBAL S*)p = in[0];
+  }
+}
+
+template <typename IT>
+__device__ __forceinline__ IT div_fixed(IT n, IT d, FastDiv f) {
+  if constexpr (sizeof(IT) == 4)
+    return fastdiv(n, f);
+  else
+    return n / d;
+}
+
+// Running maximum of |v| kept as the bits of |v|: for non-negative IEEE values
+// the integer order is the numeric order, and a NaN (any sign) compares above
+// +inf, so a NaN residual survives the maximum.
+template <typename E> struct AbsMax;
+template <> struct AbsMax<float> {
+  uint32_t b = 0;
+  __device__ __forceinline__ void add(float v) {
+    const uint32_t x = __float_as_uint(v) & 0x7fffffffu;
+    b = x > b ? x : b;
+  }
+  __device__ __forceinline__ double get() const { return (double)__uint_as_float(b); }
+};
+template <> struct AbsMax<double> {
+  uint64_t b = 0;
+  __device__ __forceinline__ void add(double v) {
+    const uint64_t x = (uint64_t)__double_as_longlong(v) & 0x7fffffffffffffffull;
+    b = x > b ? x : b;
+  }
+  __device__ __forceinline__ double get() const { return __longlong_as_double((long long)b); }
 };
 
-// Z_n at the VEC elements starting at column i of `row`, with the rank loop
-// unrolled to RP (P_n has zero rows up to kRT, U_n W_n zero columns), so that
-// all loads of P_n and U_n W_n are independent and issue together.  The sum is
-// accumulated in FP64 whatever the state type: an FP32 sum over R terms of
-// unit-scale data would carry ~R 2^-24 |Z| of error, above an absolute
-// tolerance of 1e-6.
-template <typename S, int VEC, int RP, typename IT>
-__device__ __forceinline__ void recon_row(const Problem<S>& pb, const RowGeom& rg, int n, bool last,
-                                          IT row, IT i, double z[VEC]) {
-  const ModeGeom& g = pb.g[n];
-  const ModeBufs<S>& mb = pb.m[n];
+// What the fused pass needs of one problem, read once into registers before
+// the first store (so that the compiler keeps it in scalar registers instead
+// of re-reading it after every store to Y or D).
+//
+// Row view: rows = numel / I_N of length I_N.  For a mode n < N-1 the row index
+// splits as row = (a * I_n + i_n) * Rb_n + rb with Rb_n = B_n / I_N, and the
+// mode-n unfolding column of the element in column i of the row is
+// j = a * B_n + rb * I_N + i.  For the last mode, i_N = i and j = row.
+template <typename S, int NN, typename IT>
+struct FusedView {
+  const S* T;
+  S* D;
+  S* Y[NN];
+  const S* P[NN];
+  const S* F[NN];  // U_n W_n (rows of kRT) for n < N-1, its transpose for the last mode
+  IT J[NN], I[NN], B[NN], Rb[NN];
+  IT IN, Q, nchunk;
+  FastDiv fq, frb[NN], fi[NN];
+};
+
+template <typename S, int NN, int VEC, typename IT>
+__device__ __forceinline__ FusedView<S, NN, IT> fused_view(const Problem<S>& pb) {
+  FusedView<S, NN, IT> v;
+  v.T = pb.T;
+  v.D = pb.D;
+  v.IN = (IT)pb.g[NN - 1].I;
+  v.Q = v.IN / VEC;
+  v.nchunk = (IT)(pb.numel / VEC);
+  v.fq = pb.fd_q;
 #pragma unroll
-  for (int t = 0; t < VEC; ++t) z[t] = 0.0;
-  if (last) {
+  for (int n = 0; n < NN; ++n) {
+    v.Y[n] = pb.m[n].Y;
+    v.P[n] = pb.m[n].P;
+    v.F[n] = n < NN - 1 ? pb.m[n].Uf : pb.m[n].UfT;
+    v.J[n] = (IT)pb.g[n].J;
+    v.I[n] = (IT)pb.g[n].I;
+    v.B[n] = (IT)pb.g[n].B;
+    v.Rb[n] = (IT)(pb.g[n].B / pb.g[NN - 1].I);
+    v.frb[n] = pb.fd_rb[n];
+    v.fi[n] = pb.fd_i[n];
+  }
+  return v;
+}
+
+// Z_n at the VEC elements starting at column i of `row`, accumulated in the
+// state type, with the rank loop unrolled to RP (P_n has zero rows up to kRT
+// and U_n W_n zero columns).  A scheduling barrier after the loads keeps them
+// issued together: left alone, the compiler interleaves loads and FMAs to save
+// registers and waits on each load in turn.
+template <typename S, int NN, int VEC, int RP, typename IT>
+__device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
+                                          S z[VEC]) {
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) z[t] = S(0);
+  if (n == NN - 1) {
     S pr[RP];
     S u[RP][VEC];
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
-      pr[r] = mb.P[(int64_t)r * g.J + row];
-      loadv<S, VEC>(mb.UfT + (int64_t)r * g.I, i, u[r]);
+      gload<S, 1, IT>(v.P[n], (IT)r * v.J[n] + row, &pr[r]);
+      gload<S, VEC, IT>(v.F[n], (IT)r * v.IN + i, u[r]);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < RP; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] = fma((double)u[r][t], (double)pr[r], z[t]);
+      for (int t = 0; t < VEC; ++t) z[t] = fma(u[r][t], pr[r], z[t]);
   } else {
-    const IT Rb = (IT)rg.Rb[n];
-    const IT q1 = Rb == 1 ? row : row / Rb;
-    const IT a = g.A == 1 ? IT(0) : q1 / (IT)g.I;
-    const IT in = q1 - a * (IT)g.I;
-    const IT j = a * (IT)g.B + (row - q1 * Rb) * (IT)rg.IN + i;
+    const IT q1 = div_fixed<IT>(row, v.Rb[n], v.frb[n]);
+    const IT a = n == 0 ? IT(0) : div_fixed<IT>(q1, v.I[n], v.fi[n]);  // A_0 = 1
+    const IT in = q1 - a * v.I[n];
+    const IT j = a * v.B[n] + (row - q1 * v.Rb[n]) * v.IN + i;
+    constexpr int W = VW<S>::n;  // U_n W_n rows are kRT long and 16-byte aligned
     S u[RP];
+#pragma unroll
+    for (int r = 0; r < RP; r += W) gload<S, W, IT>(v.F[n], in * (IT)kRT + (IT)r, &u[r]);
     S pv[RP][VEC];
 #pragma unroll
-    for (int r = 0; r < RP; ++r) {
-      u[r] = mb.Uf[(int64_t)in * kRT + r];
-      loadv<S, VEC>(mb.P + (int64_t)r * g.J, j, pv[r]);
-    }
+    for (int r = 0; r < RP; ++r) gload<S, VEC, IT>(v.P[n], (IT)r * v.J[n] + j, pv[r]);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < RP; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] = fma((double)u[r], (double)pv[r][t], z[t]);
+      for (int t = 0; t < VEC; ++t) z[t] = fma(u[r], pv[r][t], z[t]);
   }
 }
 
 // One problem's share of the fused pass: `nblk` blocks of which this is `lblk`.
-// Arithmetic in FP64 registers; D and Y_n are rounded to the state type when
-// stored, and the residual and the multiplier update use the stored D, so the
-// stored iterate satisfies Y_n^{k+1} - Y_n^k = mu (D - Z_n) up to Y's rounding.
+// The arithmetic is in the state type: every quantity is formed with one
+// rounding from stored state-type values (D - Z_n of two nearby values is
+// exact, Y_n + mu (D - Z_n) is one fused multiply-add), so wider registers would
+// change the stored iterate only through the rounding of mu.  The residual is
+// taken from the stored D.
 template <typename S, int NN, int VEC, int RP, typename IT>
 __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk) {
-  RowGeom rg;
-  rg.IN = (uint64_t)pb.g[NN - 1].I;
-#pragma unroll
-  for (int n = 0; n < NN - 1; ++n) rg.Rb[n] = (uint64_t)pb.g[n].B / rg.IN;
-  const double mu = pb.sc->mu;
-  const double inv_mu = 1.0 / mu;
-  const double theta = 1.0 / (mu * NN);
-  const double invN = 1.0 / NN;
-  double rmax[NN + 1];  // residual of every mode, then max |D|
-#pragma unroll
-  for (int n = 0; n <= NN; ++n) rmax[n] = 0.0;
-  const IT nchunk = (IT)(pb.numel / VEC);
-  const IT Q = (IT)(rg.IN / VEC);
-  for (IT c = (IT)lblk * blockDim.x + threadIdx.x; c < nchunk; c += (IT)nblk * blockDim.x) {
-    const IT row = c / Q;
-    const IT i = (c - row * Q) * VEC;
+  const FusedView<S, NN, IT> v = fused_view<S, NN, VEC, IT>(pb);
+  const double mu_d = pb.sc->mu;
+  const S mu = (S)mu_d;
+  const S inv_mu = (S)(1.0 / mu_d);
+  const S theta = (S)(1.0 / (mu_d * NN));
+  const S invN = (S)(1.0 / NN);
+  AbsMax<S> rmax[NN + 1];  // residual of every mode, then max |D|
+  for (IT c = (IT)lblk * blockDim.x + threadIdx.x; c < v.nchunk; c += (IT)nblk * blockDim.x) {
+    const IT row = div_fixed<IT>(c, v.Q, v.fq);
+    const IT i = (c - row * v.Q) * VEC;
     const IT x0 = c * VEC;
     S tv[VEC];
-    loadv<S, VEC>(pb.T, x0, tv);
-    double z[NN][VEC];
+    gload<S, VEC, IT>(v.T, x0, tv);
+    S z[NN][VEC];
     S y[NN][VEC];
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      recon_row<S, VEC, RP, IT>(pb, rg, n, n == NN - 1, row, i, z[n]);
-      loadv<S, VEC>(pb.m[n].Y, x0, y[n]);
+      recon_row<S, NN, VEC, RP, IT>(v, n, row, i, z[n]);
+      gload<S, VEC, IT>(v.Y[n], x0, y[n]);
     }
     S dv[VEC];
 #pragma unroll
     for (int t = 0; t < VEC; ++t) {
-      double sum = 0.0;
+      S sum = S(0);
 #pragma unroll
-      for (int n = 0; n < NN; ++n) sum += (double)y[n][t] * inv_mu - z[n][t];
-      const double m = sum * invN;
-      const double tt = (double)tv[t];
-      const double h = tt + m;
-      dv[t] = (S)((fabs(h) <= theta) ? tt : (copysign(theta, h) - m));
-      const double d = (double)dv[t];
+      for (int n = 0; n < NN; ++n) sum += y[n][t] * inv_mu - z[n][t];
+      const S m = sum * invN;
+      const S h = tv[t] + m;
+      const S d = (fabs(h) <= theta) ? tv[t] : (copysign(theta, h) - m);
+      dv[t] = d;
 #pragma unroll
       for (int n = 0; n < NN; ++n) {
-        const double res = d - z[n][t];
-        y[n][t] = (S)((double)y[n][t] + mu * res);
-        rmax[n] = nanmax(rmax[n], fabs(res));
+        const S res = d - z[n][t];
+        y[n][t] = fma(mu, res, y[n][t]);
+        rmax[n].add(res);
       }
-      rmax[NN] = nanmax(rmax[NN], fabs(d));
+      rmax[NN].add(d);
     }
-    storev<S, VEC>(pb.D, x0, dv);
+    gstore<S, VEC, IT>(v.D, x0, dv);
 #pragma unroll
-    for (int n = 0; n < NN; ++n) storev<S, VEC>(pb.m[n].Y, x0, y[n]);
+    for (int n = 0; n < NN; ++n) gstore<S, VEC, IT>(v.Y[n], x0, y[n]);
   }
-  block_residual_max<NN + 1>(pb.sc, rmax, lblk);
+  double r[NN + 1];
+#pragma unroll
+  for (int n = 0; n <= NN; ++n) r[n] = rmax[n].get();
+  block_residual_max<NN + 1>(pb.sc, r, lblk);
 }
 
 // The fused pass over a batch; each problem takes the 16-byte vector path when
@@ -348,11 +426,11 @@ template <typename S, int NN, int RP>
 static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.fused_blocks; });
-  bool big = false;
-  for (int r = 0; r < ls.count; ++r) big = big || ls.host[r]->numel >= (int64_t(1) << 31);
-  if (!big)
+  bool idx32 = true;
+  for (int r = 0; r < ls.count; ++r) idx32 = idx32 && ls.host[r]->idx32;
+  if (idx32)
     hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t>), dim3(grid), dim3(256), 0, s, b);
-  else  // tensors of 2^31 elements or more: 64-bit indexing, full rank tile
+  else  // offsets beyond 32 bits: 64-bit indexing, full rank tile
     hipLaunchKernelGGL((k_fused<S, NN, kRT, uint64_t>), dim3(grid), dim3(256), 0, s, b);
 }
 

@@ -12,6 +12,25 @@ constexpr int kMaxN = PASD_MAX_ORDER;
 constexpr int kRT = 16;        // rank tile: R_n is padded to 16 in the factors and partials
 constexpr int kResSlots = 64;  // residual maxima are spread over this many words per mode
 
+// Division by a divisor d >= 1 fixed for a whole launch, by multiply-high,
+// add and shift (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, the round-up method): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, n / d = (umulhi(n, m) + n) >> l for
+// 0 <= n < 2^32; kernels use it for n < 2^31, where the sum cannot overflow.
+struct FastDiv {
+  uint32_t m, l;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  const uint64_t m = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+  return FastDiv{(uint32_t)m, l};
+}
+__host__ __device__ inline uint32_t fastdiv(uint32_t n, FastDiv f) {
+  const uint32_t hi = (uint32_t)(((uint64_t)n * f.m) >> 32);
+  return (hi + n) >> f.l;
+}
+
 // Geometry of the mode-n unfolding of a row-major tensor viewed as (A, I, B):
 // element (a, i, b) sits at a*I*B + i*B + b, column index j = a*B + b.
 struct ModeGeom {
@@ -79,6 +98,12 @@ struct Problem {
   int kb[KB_COUNT][kMaxN + 1];
   int fused_blocks;  // blocks of the fused pass for this problem
   int vecw;          // last dimension divisible by the 16-byte vector width (fused pass)
+  int idx32;         // every element offset of the fused pass fits 32-bit byte offsets
+  // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
+  // the rows per mode-n fibre index (B_n / I_N) and I_n
+  FastDiv fd_q;
+  FastDiv fd_rb[kMaxN];
+  FastDiv fd_i[kMaxN];
 };
 
 // One launch over up to kMaxBatch problems (kernel arguments, ~1.6 KB): block

@@ -215,6 +215,18 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   const int vw = 16 / (int)sizeof(S);
   p.vecw = (p.g[ctx->N - 1].I % vw) == 0 ? 1 : 0;
   p.fused_blocks = fused_blocks(p.numel, p.vecw ? vw : 1);
+  // 32-bit offsets in the fused pass when every element offset, and every
+  // index divided there, stays below 2^31 bytes
+  int64_t span = p.numel;
+  for (int n = 0; n < ctx->N; ++n) span = std::max<int64_t>(span, (int64_t)kRT * p.g[n].J);
+  p.idx32 = span * (int64_t)sizeof(S) < (int64_t(1) << 31) ? 1 : 0;
+  const int64_t IN = p.g[ctx->N - 1].I;
+  p.fd_q = make_fastdiv((uint32_t)(p.idx32 ? IN / (p.vecw ? vw : 1) : 1));
+  for (int n = 0; n < kMaxN; ++n) {
+    const bool inner = n < ctx->N - 1 && p.idx32;
+    p.fd_rb[n] = make_fastdiv((uint32_t)(inner ? p.g[n].B / IN : 1));
+    p.fd_i[n] = make_fastdiv((uint32_t)(inner ? p.g[n].I : 1));
+  }
 }
 
 // Enqueue `count` iterations; with `ev` non-null an event is recorded before
