@@ -121,15 +121,25 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
       // clamped to a valid row and masked), so unrolled iterations overlap
       const S* __restrict__ Db = pb.D + off[0];
       const S* __restrict__ Yb = mb.Y + off[0];
-#pragma unroll 4
-      for (int i0 = kbeg; i0 < kend; i0 += 4) {
-        const bool ok = i0 + q < kend;
-        const int i = ok ? i0 + q : kbeg;
-        const V d = *reinterpret_cast<const V*>(Db + (int64_t)i * g.B);
-        const V y = *reinterpret_cast<const V*>(Yb + (int64_t)i * g.B);
-        const S u = ok ? Us[(int64_t)i * kRT + p] : S(0);
+      // four K-steps (16 rows) per pass, all loads issued before the MFMAs;
+      // a masked row contributes u = 0 times a finite value of a valid row
+      for (int i0 = kbeg; i0 < kend; i0 += 16) {
+        V d[4], y[4];
+        S u[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u, ok ? d[t] + y[t] * inv_mu : S(0), acc[t]);
+        for (int k = 0; k < 4; ++k) {
+          const bool ok = i0 + 4 * k + q < kend;
+          const int i = ok ? i0 + 4 * k + q : kbeg;
+          d[k] = *reinterpret_cast<const V*>(Db + (int64_t)i * g.B);
+          y[k] = *reinterpret_cast<const V*>(Yb + (int64_t)i * g.B);
+          const S uu = Us[(int64_t)i * kRT + p];
+          u[k] = ok ? uu : S(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u[k], d[k][t] + y[k][t] * inv_mu, acc[t]);
       }
     } else {
       for (int i0 = kbeg; i0 < kend; i0 += 4) {
@@ -180,18 +190,28 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
       const int64_t ar = rowok ? arow : g.A - 1;
       const S* __restrict__ Db = pb.D + ar * g.I;
       const S* __restrict__ Yb = mb.Y + ar * g.I;
-#pragma unroll 4
-      for (int i0 = 0; i0 < g.I; i0 += 16) {
-        const int iq = i0 + 4 * q;
-        const bool ok = iq < g.I;
-        const int i = ok ? iq : g.I - 4;
-        const V d = *reinterpret_cast<const V*>(Db + i);
-        const V y = *reinterpret_cast<const V*>(Yb + i);
+      // four 16-wide chunks per pass, all loads issued before the MFMAs
+      for (int i0 = 0; i0 < g.I; i0 += 64) {
+        V d[4], y[4];
+        S u[4][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const S u = ok ? Us[(int64_t)(i + t) * kRT + p] : S(0);
-          acc = MM<S>::mma((ok && rowok) ? d[t] + y[t] * inv_mu : S(0), u, acc);
+        for (int k = 0; k < 4; ++k) {
+          const int iq = i0 + 16 * k + 4 * q;
+          const bool ok = iq < g.I;
+          const int i = ok ? iq : g.I - 4;
+          d[k] = *reinterpret_cast<const V*>(Db + i);
+          y[k] = *reinterpret_cast<const V*>(Yb + i);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const S uu = Us[(int64_t)(i + t) * kRT + p];
+            u[k][t] = (ok && rowok) ? uu : S(0);
+          }
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc = MM<S>::mma(d[k][t] + y[k][t] * inv_mu, u[k][t], acc);
       }
     } else {
       for (int i0 = 0; i0 < g.I; i0 += 16) {
@@ -253,7 +273,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   double* __restrict__ out = mb.Mpart + (int64_t)blk * g.I * kRT;
 
   if (g.B > 1) {
-    constexpr int IBP = 8;  // row blocks per pass
+    constexpr int IBP = sizeof(S) == 4 ? 8 : 4;  // row blocks per pass (register budget)
     const int64_t nsteps = (g.J + 15) / 16;
     const int64_t per_blk = (nsteps + mb.mblocks - 1) / mb.mblocks;
     const int64_t sbeg = (int64_t)blk * per_blk;
@@ -490,12 +510,24 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
   const bool pvec = (g.J % 4) == 0;
   d4v acc = d4v{0, 0, 0, 0};
   // full 16-column steps: unconditional vector loads of row p (rows R..15 of
-  // P_n are zero), so the unrolled iterations keep several loads in flight
+  // P_n are zero), kGramU steps of this wave per pass with all their loads
+  // issued before the first MFMA
+  constexpr int kGramU = 8;
   const int64_t full_end = pvec ? min(send, g.J / 16) : sbeg;
+  const S* prow = mb.P + (int64_t)p * g.J + 4 * q;
   int64_t st = sbeg + wave;
-#pragma unroll 4
+  for (; st + 4 * (kGramU - 1) < full_end; st += 4 * kGramU) {
+    V v[kGramU];
+#pragma unroll
+    for (int u = 0; u < kGramU; ++u) v[u] = *reinterpret_cast<const V*>(prow + (st + 4 * u) * 16);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < kGramU; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc = mma64((double)v[u][t], (double)v[u][t], acc);
+  }
   for (; st < full_end; st += 4) {
-    const V v = *reinterpret_cast<const V*>(mb.P + (int64_t)p * g.J + st * 16 + 4 * q);
+    const V v = *reinterpret_cast<const V*>(prow + st * 16);
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc = mma64((double)v[t], (double)v[t], acc);
   }
@@ -544,7 +576,7 @@ int gemm_m_blocks(const ModeGeom& g) {
 
 int gram_blocks(const ModeGeom& g) {
   const int64_t steps = (g.J + 15) / 16;
-  int64_t want = 16;
+  int64_t want = 32;
   int64_t maxb = (steps + 3) / 4;
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }

@@ -132,16 +132,27 @@ __global__ void __launch_bounds__(64) k_qr(Batch<S> bt) {
 }
 
 // ---------------------------------------------------------------------------
-// SVT factor by a warm-started parallel cyclic Jacobi on the R x R Gram.
-//  1. S = sum of the Gram partials (all 256 threads, independent loads);
+// SVT factor by a warm-started parallel cyclic Jacobi on the R x R Gram, one
+// 256-thread block per (problem, mode):
+//  1. S = sum of the Gram partials (one entry per thread, all partials loaded
+//     at once) while U_n is staged in LDS;
 //  2. S' = W0^T S W0 with W0 the eigenvectors of the previous iteration
 //     (identity at k = 0), so that S' is nearly diagonal once the iteration
 //     settles; the eigenvectors are accumulated as W = W0 J_1 J_2 ...;
-//  3. round-robin Jacobi: every round rotates R'/2 disjoint pairs (R' = R
-//     rounded up to even, a dummy index for odd R), one lane per 2x2 block;
-//  4. W_f = W diag(f) W^T, U W_f from U staged in LDS.
+//  3. before each sweep the block checks whether any pair still needs a
+//     rotation, so a converged matrix costs one check instead of a sweep;
+//  4. round-robin Jacobi: every round rotates R'/2 disjoint pairs (R' = R
+//     rounded up to even, a dummy index for odd R), one lane per pair, with
+//     the rotation in Rutishauser's form: for x = s_qq - s_pp, y = 2 s_pq,
+//     r = hypot(x, y), w = |x| + r: c = w / hypot(w, y), s = sgn(x) y / hypot(w, y),
+//     t = s / c = sgn(x) y / w;
+//  5. W_f = W diag(f) W^T and U W_f.
+// A pair is rotated while |s_pq| > thr sqrt(|s_pp s_qq|), thr = 4e-16 for an
+// FP64 state and 1e-10 for FP32, whose factors U W_f are rounded to 2^-24.
 // W_f is a spectral function of S, so it does not depend on W0 beyond rounding.
 // ---------------------------------------------------------------------------
+constexpr int kEigParts = 32;  // Gram partials summed in one pass of loads
+
 template <typename S>
 __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
@@ -155,51 +166,74 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   __shared__ double Sm[kRT][kRT + 1];
   __shared__ double W[kRT][kRT + 1];
   __shared__ double T1[kRT][kRT + 1];
-  __shared__ double cs[kRT / 2][2];
+  __shared__ double rot[kRT / 2][3];  // c, s, t of each pair of the round
   __shared__ int pq[kRT / 2][2];
   __shared__ double fac[kRT];
   __shared__ double Ul[kQrLds];
   {
-    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (r < R && c < R) {
-      const double* sp = mb.Spart + tid;
-      const int nb = mb.sblocks;
-      int b = 0;
-      for (; b + 8 <= nb; b += 8) {
+    const int r = tid / kRT, c = tid % kRT;
+    const bool in = r < R && c < R;
+    // all loads of this thread first: its share of U_n, then the partials
+    constexpr int kU = 8;
+    double uv[kU];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += sp[(int64_t)(b + u) * kRT * kRT];
-      }
-      for (; b < nb; ++b) acc[0] += sp[(int64_t)b * kRT * kRT];
+    for (int u = 0; u < kU; ++u) {
+      const int e = tid + 256 * u;
+      uv[u] = e < I * R ? mb.U[e] : 0.0;
     }
-    Sm[r][c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-    W[r][c] = (warm && r < R && c < R) ? mb.Wev[tid] : (r == c ? 1.0 : 0.0);
+    const int nb = mb.sblocks;
+    const double* sp = mb.Spart + tid;
+    double part[kEigParts];
+#pragma unroll
+    for (int b = 0; b < kEigParts; ++b) part[b] = (in && b < nb) ? sp[(int64_t)b * kRT * kRT] : 0.0;
+    for (int b = kEigParts; b < nb; ++b)
+      if (in) part[b % kEigParts] += sp[(int64_t)b * kRT * kRT];
+    // fixed-order pairwise sum of the partials
+#pragma unroll
+    for (int w = kEigParts / 2; w > 0; w /= 2)
+#pragma unroll
+      for (int b = 0; b < w; ++b) part[b] += part[b + w];
+    Sm[r][c] = part[0];
+    W[r][c] = (warm && in) ? mb.Wev[tid] : (r == c ? 1.0 : 0.0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int e = tid + 256 * u;
+      if (e < I * R) Ul[e] = uv[u];
+    }
+    for (int e = tid + 256 * kU; e < I * R; e += 256) Ul[e] = mb.U[e];
   }
-#pragma unroll 8
-  for (int e = tid; e < I * R; e += 256) Ul[e] = mb.U[e];
   __syncthreads();
-  {  // T1 = S W0 (upper triangle of S mirrored), then S' = W0^T T1, upper triangle mirrored
-    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
+  {  // T1 = S W0 with the upper triangle of S mirrored
+    const int r = tid / kRT, c = tid % kRT;
     double t = 0;
     for (int k = 0; k < R; ++k) t += (r <= k ? Sm[r][k] : Sm[k][r]) * W[k][c];
     T1[r][c] = t;
   }
   __syncthreads();
-  {
-    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
-    double t = 0;
+  {  // S' = W0^T T1, upper triangle mirrored
+    const int r = tid / kRT, c = tid % kRT;
     const int rr = r <= c ? r : c, cc = r <= c ? c : r;
-    for (int k = 0; k < R; ++k) t += W[k][rr] * T1[k][cc];
+    double v = 0;
+    for (int k = 0; k < R; ++k) v += W[k][rr] * T1[k][cc];
     __syncthreads();
-    Sm[r][c] = (r < R && c < R) ? t : 0.0;
+    Sm[r][c] = (r < R && c < R) ? v : 0.0;
   }
   __syncthreads();
+  const double thr = sizeof(S) == 4 ? 1.0e-10 : 4.0e-16;
   const int Rp = R + (R & 1);
   const int half = Rp / 2;
   const int m = Rp - 1;
   int sweeps = 0;
-  for (int sweep = 0; sweep < 40 && Rp > 1; ++sweep) {
-    int rotated = 0;
+  for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
+    int need = 0;
+    {
+      const int p = tid / kRT, q = tid % kRT;
+      if (p < q && q < R) {
+        const double b = fabs(Sm[p][q]);
+        need = b > 1e-300 && b > thr * sqrt(fabs(Sm[p][p])) * sqrt(fabs(Sm[q][q]));
+      }
+    }
+    if (!__syncthreads_or(need)) break;
     sweeps = sweep + 1;
     for (int rd = 0; rd < m; ++rd) {
       if (tid < half) {
@@ -216,65 +250,69 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
           p = q;
           q = tmp;
         }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, s = 0.0, t = 0.0;
         if (q < R) {
           const double a = Sm[p][p], d = Sm[q][q], b = Sm[p][q];
           const double ab = fabs(b);
-          if (ab > 1e-300 && ab > 4.0e-16 * sqrt(fabs(a)) * sqrt(fabs(d))) {
-            const double th = (d - a) / (2.0 * b);
-            const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            rotated = 1;
+          if (ab > 1e-300 && ab > thr * sqrt(fabs(a)) * sqrt(fabs(d))) {
+            const double x = d - a, y = 2.0 * b;
+            const double r = sqrt(x * x + y * y);
+            const double w = fabs(x) + r;
+            const double sy = x >= 0.0 ? y : -y;
+            const double h = 1.0 / sqrt(w * w + y * y);
+            c = w * h;
+            s = sy * h;
+            t = sy / w;
           }
         }
-        cs[tid][0] = c;
-        cs[tid][1] = s;
+        rot[tid][0] = c;
+        rot[tid][1] = s;
+        rot[tid][2] = t;
         pq[tid][0] = p;
         pq[tid][1] = q;
       }
-      rotated = __syncthreads_or(rotated);
-      if (tid < half * half && tid / half <= tid % half) {
+      __syncthreads();
+      if (tid < half * half) {
         const int k = tid / half, l = tid - k * half;
-        const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
-        const double ck = cs[k][0], sk = cs[k][1], cl = cs[l][0], sl = cs[l][1];
-        const double x00 = Sm[pk][pl], x01 = Sm[pk][ql], x10 = Sm[qk][pl], x11 = Sm[qk][ql];
-        // rows: J_k^T
-        const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
-        const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
-        // columns: J_l
-        double z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
-        double z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
-        if (k == l && sk != 0.0) {
-          // diagonal block: the rotation annihilates the off-diagonal entry
-          const double b = x01;
-          const double t = sk / ck;
-          z00 = x00 - t * b;
-          z11 = x11 + t * b;
-          z01 = 0.0;
-          z10 = 0.0;
+        if (k <= l) {
+          const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
+          const double ck = rot[k][0], sk = rot[k][1], cl = rot[l][0], sl = rot[l][1];
+          const double x00 = Sm[pk][pl], x01 = Sm[pk][ql], x10 = Sm[qk][pl], x11 = Sm[qk][ql];
+          // rows: J_k^T
+          const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
+          const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
+          // columns: J_l
+          double z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
+          double z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
+          if (k == l && sk != 0.0) {
+            // diagonal block: the rotation annihilates the off-diagonal entry
+            const double tb = rot[k][2] * x01;
+            z00 = x00 - tb;
+            z11 = x11 + tb;
+            z01 = 0.0;
+            z10 = 0.0;
+          }
+          // blocks (k, l) and (l, k) are mirror images: write both from one lane
+          Sm[pk][pl] = z00;
+          Sm[pk][ql] = z01;
+          Sm[qk][pl] = z10;
+          Sm[qk][ql] = z11;
+          Sm[pl][pk] = z00;
+          Sm[ql][pk] = z01;
+          Sm[pl][qk] = z10;
+          Sm[ql][qk] = z11;
         }
-        // blocks (k, l) and (l, k) are mirror images: write both from one lane
-        Sm[pk][pl] = z00;
-        Sm[pk][ql] = z01;
-        Sm[qk][pl] = z10;
-        Sm[qk][ql] = z11;
-        Sm[pl][pk] = z00;
-        Sm[ql][pk] = z01;
-        Sm[pl][qk] = z10;
-        Sm[ql][qk] = z11;
-      }
-      if (tid < kRT * half) {
-        const int i = tid / half, l = tid - (tid / half) * half;
+      } else if (tid >= 64 && tid < 64 + R * half) {
+        const int t = tid - 64;
+        const int i = t / half, l = t - (t / half) * half;
         const int pl = pq[l][0], ql = pq[l][1];
-        const double cl = cs[l][0], sl = cs[l][1];
+        const double cl = rot[l][0], sl = rot[l][1];
         const double wp = W[i][pl], wq = W[i][ql];
         W[i][pl] = cl * wp - sl * wq;
         W[i][ql] = sl * wp + cl * wq;
       }
       __syncthreads();
     }
-    if (!rotated) break;
   }
   if (tid == 0) pb.sc->eig_sweeps[n] = sweeps;
   const double tau = pb.lam[n] / pb.sc->mu;
@@ -289,13 +327,11 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   }
   __syncthreads();
   if (tid < 64) {
-    int cnt = (tid < R && fac[tid] > 0.0) ? 1 : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    const int cnt = __popcll(__ballot(tid < R && fac[tid < kRT ? tid : 0] > 0.0));
     if (tid == 0) pb.sc->rank[n] = cnt;
   }
   {
-    const int r = tid / kRT, c = tid - (tid / kRT) * kRT;
+    const int r = tid / kRT, c = tid % kRT;
     double s = 0.0;
     if (r < R && c < R)
       for (int i = 0; i < R; ++i) s += W[r][i] * fac[i] * W[c][i];
@@ -304,13 +340,34 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
     mb.Wev[tid] = (r < R && c < R) ? W[r][c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int e = tid; e < I * kRT; e += 256) {
-    const int i = e / kRT, c = e - (e / kRT) * kRT;
-    double s = 0.0;
-    if (c < R)
-      for (int r = 0; r < R; ++r) s += Ul[i * R + r] * T1[r][c];
-    mb.Uf[e] = (S)s;
-    mb.UfT[(int64_t)c * I + i] = (S)s;
+  // U W_f: thread (c, i0) = (tid % 16, tid / 16) forms column c of rows
+  // i0, i0 + 16, ... with column c of W_f in registers, four rows at a time
+  {
+    const int c = tid % kRT;
+    double wf[kRT];
+#pragma unroll
+    for (int r = 0; r < kRT; ++r) wf[r] = T1[r][c];
+    for (int i0 = tid / kRT; i0 < I; i0 += 4 * (256 / kRT)) {
+      // fully unrolled over the 16 rank slots (W_f is zero beyond R, the
+      // U reads are masked) so that wf stays in fixed registers
+      double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < kRT; ++r) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = min(i0 + u * (256 / kRT), I - 1);
+          s[u] += (r < R ? Ul[i * R + r] : 0.0) * wf[r];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * (256 / kRT);
+        if (i < I) {
+          mb.Uf[(int64_t)i * kRT + c] = (S)s[u];
+          mb.UfT[(int64_t)c * I + i] = (S)s[u];
+        }
+      }
+    }
   }
 }
 
@@ -435,104 +492,6 @@ __device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&
       }
     }
     qr_form_col<C - 1, TR, RP>(a, tau, R, lane, lds);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Householder QR with the I x R matrix held in registers of one wave: lane l
-// owns rows l, l + 64, ..., the column loop is unrolled to RP (R <= RP) so
-// every register index is static, and the dot products of one column step
-// are reduced together across the wave.
-// ---------------------------------------------------------------------------
-// One Householder step on column C (compile-time, so every register index is
-// static): reflect rows >= C of columns > C, store v below the diagonal.
-template <int C, int TR, int RP>
-__device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)[RP], int R,
-                                              int lane) {
-  if constexpr (C < RP) {
-    if (C < R) {
-      double part = 0;
-#pragma unroll
-      for (int t = 0; t < TR; ++t)
-        if (lane + 64 * t > C) part += a[t][C] * a[t][C];
-      const double xnorm2 = wave_sum(part);
-      const double alpha = __shfl(a[0][C], C, 64);
-      double tc = 0, beta = alpha, scale = 0;
-      if (xnorm2 > 0) {
-        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-        tc = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      double v[TR];
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const int i = lane + 64 * t;
-        v[t] = i > C ? a[t][C] * scale : (i == C ? 1.0 : 0.0);
-      }
-      double w[RP];
-#pragma unroll
-      for (int j = 0; j < RP; ++j) {
-        double s = 0;
-        if (j > C) {
-#pragma unroll
-          for (int t = 0; t < TR; ++t) s += v[t] * a[t][j];
-        }
-        w[j] = s;
-      }
-#pragma unroll
-      for (int j = 0; j < RP; ++j)
-        if (j > C) w[j] = wave_sum(w[j]);
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-#pragma unroll
-        for (int j = 0; j < RP; ++j)
-          if (j > C) a[t][j] -= tc * w[j] * v[t];
-        const int i = lane + 64 * t;
-        if (i > C) a[t][C] = v[t];
-        if (i == C) a[t][C] = beta;
-      }
-      tau[C] = tc;
-    }
-    qr_factor_col<C + 1, TR, RP>(a, tau, R, lane);
-  }
-}
-
-// Backward accumulation of Q = H_0 ... H_{R-1} [I_R; 0], column C down to 0.
-template <int C, int TR, int RP>
-__device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&tau)[RP], int R,
-                                            int lane) {
-  if constexpr (C >= 0) {
-    if (C < R) {
-      const double tc = tau[C];
-      double v[TR];
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-        const int i = lane + 64 * t;
-        v[t] = i > C ? a[t][C] : (i == C ? 1.0 : 0.0);
-      }
-      double w[RP];
-#pragma unroll
-      for (int j = 0; j < RP; ++j) {
-        double s = 0;
-        if (j > C) {
-#pragma unroll
-          for (int t = 0; t < TR; ++t) s += v[t] * a[t][j];
-        }
-        w[j] = s;
-      }
-#pragma unroll
-      for (int j = 0; j < RP; ++j)
-        if (j > C) w[j] = wave_sum(w[j]);
-#pragma unroll
-      for (int t = 0; t < TR; ++t) {
-#pragma unroll
-        for (int j = 0; j < RP; ++j)
-          if (j > C) a[t][j] -= tc * w[j] * v[t];
-        const int i = lane + 64 * t;
-        a[t][C] = i > C ? -tc * v[t] : (i == C ? 1.0 - tc : 0.0);
-      }
-    }
-    qr_form_col<C - 1, TR, RP>(a, tau, R, lane);
   }
 }
 
