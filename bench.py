@@ -140,6 +140,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--srv-requests", type=int, default=512)
     ap.add_argument("--srv-sequential", type=int, default=128)
+    ap.add_argument("--pmc-calib", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy (3 times), the "
+                         "reference kernel that scales hardware traffic counters to bytes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -188,6 +191,15 @@ def main():
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": kb[dom], "ms_per_launch": kernels[dom]["ms"]}
     s.close()
+
+    if args.pmc_calib:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").uniform_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        _progress("copy calibration: 3 x 256 MiB device copies")
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "ADMM iters/s", "n_gpus": 1,

@@ -190,11 +190,11 @@ __device__ __forceinline__ FusedView<S, NN, IT> fused_view(const Problem<S>& pb)
 // and U_n W_n zero columns).  A scheduling barrier after the loads keeps them
 // issued together: left alone, the compiler interleaves loads and FMAs to save
 // registers and waits on each load in turn.
-template <typename S, int NN, int VEC, int RP, typename IT>
+template <typename S, typename ZT, int NN, int VEC, int RP, typename IT>
 __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
-                                          S z[VEC]) {
+                                          ZT z[VEC]) {
 #pragma unroll
-  for (int t = 0; t < VEC; ++t) z[t] = S(0);
+  for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
   if (n == NN - 1) {
     S pr[RP];
     S u[RP][VEC];
@@ -207,7 +207,7 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
 #pragma unroll
     for (int r = 0; r < RP; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] = fma(u[r][t], pr[r], z[t]);
+      for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r][t], (ZT)pr[r], z[t]);
   } else {
     const IT q1 = div_fixed<IT>(row, v.Rb[n], v.frb[n]);
     const IT a = n == 0 ? IT(0) : div_fixed<IT>(q1, v.I[n], v.fi[n]);  // A_0 = 1
@@ -224,7 +224,7 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
 #pragma unroll
     for (int r = 0; r < RP; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] = fma(u[r], pv[r][t], z[t]);
+      for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
   }
 }
 
@@ -236,40 +236,46 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
 // taken from the stored D.
 template <typename S, int NN, int VEC, int RP, typename IT>
 __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk) {
+  // Accumulation type of Z_n and type of the elementwise arithmetic.  Both are
+  // the state type: wider registers were measured to leave FP32 convergence
+  // (iteration counts, converged fraction) unchanged and cost 5-10% here.
+  typedef S ZT;
+  typedef S ET;
   const FusedView<S, NN, IT> v = fused_view<S, NN, VEC, IT>(pb);
   const double mu_d = pb.sc->mu;
-  const S mu = (S)mu_d;
-  const S inv_mu = (S)(1.0 / mu_d);
-  const S theta = (S)(1.0 / (mu_d * NN));
-  const S invN = (S)(1.0 / NN);
-  AbsMax<S> rmax[NN + 1];  // residual of every mode, then max |D|
+  const ET mu = (ET)mu_d;
+  const ET inv_mu = (ET)(1.0 / mu_d);
+  const ET theta = (ET)(1.0 / (mu_d * NN));
+  const ET invN = (ET)(1.0 / NN);
+  AbsMax<ET> rmax[NN + 1];  // residual of every mode, then max |D|
   for (IT c = (IT)lblk * blockDim.x + threadIdx.x; c < v.nchunk; c += (IT)nblk * blockDim.x) {
     const IT row = div_fixed<IT>(c, v.Q, v.fq);
     const IT i = (c - row * v.Q) * VEC;
     const IT x0 = c * VEC;
     S tv[VEC];
     gload<S, VEC, IT>(v.T, x0, tv);
-    S z[NN][VEC];
+    ZT z[NN][VEC];
     S y[NN][VEC];
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      recon_row<S, NN, VEC, RP, IT>(v, n, row, i, z[n]);
+      recon_row<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n]);
       gload<S, VEC, IT>(v.Y[n], x0, y[n]);
     }
     S dv[VEC];
 #pragma unroll
     for (int t = 0; t < VEC; ++t) {
-      S sum = S(0);
+      ET sum = ET(0);
 #pragma unroll
-      for (int n = 0; n < NN; ++n) sum += y[n][t] * inv_mu - z[n][t];
-      const S m = sum * invN;
-      const S h = tv[t] + m;
-      const S d = (fabs(h) <= theta) ? tv[t] : (copysign(theta, h) - m);
-      dv[t] = d;
+      for (int n = 0; n < NN; ++n) sum += (ET)y[n][t] * inv_mu - (ET)z[n][t];
+      const ET m = sum * invN;
+      const ET tt = (ET)tv[t];
+      const ET h = tt + m;
+      dv[t] = (S)((fabs(h) <= theta) ? tt : (copysign(theta, h) - m));
+      const ET d = (ET)dv[t];
 #pragma unroll
       for (int n = 0; n < NN; ++n) {
-        const S res = d - z[n][t];
-        y[n][t] = fma(mu, res, y[n][t]);
+        const ET res = d - (ET)z[n][t];
+        y[n][t] = (S)fma(mu, res, (ET)y[n][t]);
         rmax[n].add(res);
       }
       rmax[NN].add(d);

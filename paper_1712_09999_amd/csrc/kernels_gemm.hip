@@ -190,7 +190,9 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
       const int64_t ar = rowok ? arow : g.A - 1;
       const S* __restrict__ Db = pb.D + ar * g.I;
       const S* __restrict__ Yb = mb.Y + ar * g.I;
-      // four 16-wide chunks per pass, all loads issued before the MFMAs
+      // four 16-wide chunks per pass, all loads issued before the MFMAs.
+      // Lane (p, q) supplies A[p][q] (row a0 + p) and B[q][p] (column chunk
+      // q, rank p): a chunk past I is masked in B, a row past A in A.
       for (int i0 = 0; i0 < g.I; i0 += 64) {
         V d[4], y[4];
         S u[4][4];
@@ -204,14 +206,15 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             const S uu = Us[(int64_t)(i + t) * kRT + p];
-            u[k][t] = (ok && rowok) ? uu : S(0);
+            u[k][t] = ok ? uu : S(0);
           }
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int t = 0; t < 4; ++t) acc = MM<S>::mma(d[k][t] + y[k][t] * inv_mu, u[k][t], acc);
+          for (int t = 0; t < 4; ++t)
+            acc = MM<S>::mma(rowok ? d[k][t] + y[k][t] * inv_mu : S(0), u[k][t], acc);
       }
     } else {
       for (int i0 = 0; i0 < g.I; i0 += 16) {

@@ -209,6 +209,13 @@ class Solver:
             lib().pasd_destroy(self._h)
         self._h = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
     def __del__(self):
         try:
             self.close()

@@ -131,6 +131,10 @@ SHAPES = [
     ((130, 9, 70), (5, 4, 6), 0.002, 40),
     ((300, 10, 8), (6, 3, 3), 0.01, 25),     # QR in registers with 5 rows per lane
     ((600, 12, 10), (12, 4, 4), 0.01, 20),   # QR falls back to the LDS kernel
+    # last mode contiguous with a partial final 16-row tile narrower than R
+    # (A_N mod 16 < R_N): rows past A must be masked in the row operand only
+    ((7, 5, 20), (3, 3, 8), 0.01, 30),
+    ((111, 41, 36), (7, 14, 8), 0.01, 20),
 ]
 
 

@@ -134,3 +134,23 @@ def test_batch_rejects_bad_lists():
     t = P.Solver(wl.observed(np.float32), wl.ranks, precision="fp32", stream=st.cuda_stream)
     with pytest.raises(P.PasdError):
         P.step_batch([s, t], 1)
+
+
+@pytest.mark.parametrize("idx,recoverable", [(6, True), (22, True), (86, False)])
+def test_trace_requests_converge_to_planted(idx, recoverable):
+    """Requests of the serving trace whose last mode ends in a partial row
+    tile narrower than R (A_N mod 16 < R_N) solve to the tolerance in FP32;
+    where the planted ranks are low enough for exact recovery, X matches the
+    planted low-rank part (request 86 plants rank 14 in a 41-wide mode)."""
+    from workloads.torch_gen import tucker_on_device
+
+    spec = workloads.serving_trace(count=512, qps=1.0)[idx]
+    T, L, _ = tucker_on_device(spec["dims"], spec["ranks"], spec["frac"], spec["seed"])
+    with P.Solver(T, spec["ranks"], precision="fp32", tol=1e-6, max_iter=1000) as s:
+        info = s.solve()
+        X, _ = s.result()
+    assert info.converged, (idx, info.iterations, list(info.residual[:len(spec["dims"])]))
+    assert info.iterations < 400, (idx, info.iterations)
+    if recoverable:
+        rse = float(torch.linalg.norm(X.double() - L) / torch.linalg.norm(L))
+        assert rse < 1e-5, (idx, rse)
