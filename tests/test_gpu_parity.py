@@ -152,6 +152,47 @@ def test_shapes(dims, ranks, mu0, iters, precision):
     _compare(st, s, precision, f"{dims}/{ranks}/{precision}")
 
 
+def _random_case(seed):
+    """A seeded random problem: order 2-4, dimensions 3..48 (3..16 for order
+    4; every other one a multiple of 4, so that both the scalar and the vector
+    paths of the last mode and both GEMM schemes with partial tiles appear),
+    Tucker-feasible ranks up to min(16, I_n), planted with the same ranks."""
+    rng = np.random.default_rng(900_000 + seed)
+    N = 2 + seed % 3
+    while True:
+        dims = []
+        for n in range(N):
+            d = int(rng.integers(3, 49 if N < 4 else 17))
+            if (seed + n) % 2 == 0:
+                d = max(4, d // 4 * 4)
+            dims.append(d)
+        if int(np.prod(dims)) <= 40_000:
+            break
+        if N > 2:
+            N -= 1
+    ranks = [int(rng.integers(1, min(16, d) + 1)) for d in dims]
+    for _ in range(8):  # Tucker feasibility: r_n <= prod_{m != n} r_m
+        for n in range(N):
+            others = int(np.prod([ranks[m] for m in range(N) if m != n]))
+            ranks[n] = min(ranks[n], others)
+    return tuple(dims), tuple(ranks)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("seed", range(16))
+def test_random_shapes(seed, precision):
+    dims, ranks = _random_case(seed)
+    wl = workloads.tucker_workload("rand", dims, ranks, 0.08, 4321 + seed,
+                                   value_range=(-5, 5), scale="rms", ranks=ranks)
+    T = wl.observed(np.float32 if precision == "fp32" else np.float64).astype(np.float64)
+    mu0 = 0.02
+    st = pasd_init(T, ranks, mu0=mu0)
+    pasd_iterate(st, 20)
+    s = _gpu(T, ranks, precision, mu0=mu0)
+    s.step(20)
+    _compare(st, s, precision, f"random {seed}: {dims}/{ranks}/{precision}")
+
+
 # --------------------------------------------------------------------------- full size (200^3)
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
