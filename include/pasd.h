@@ -56,9 +56,11 @@ enum pasd_precision {
   PASD_FP64 = 0,      /* FP64 state and arithmetic throughout */
   PASD_FP32 = 1,      /* FP32 state and unfolding GEMMs (FP32 MFMA); FP64 QR,
                          Gram, eigensolver, scalars */
-  PASD_BF16_GEMM = 2  /* FP32 state; unfolding GEMM inputs rounded to BF16
-                         (round-to-nearest-even) with FP32 accumulation;
-                         FP64 QR, Gram, eigensolver, scalars */
+  PASD_BF16_GEMM = 2  /* FP32 state; both operands of the unfolding GEMMs
+                         (G_n and P_n for M_n, U_n and G_n for P_n) rounded
+                         to BF16 (round-to-nearest-even) with FP32
+                         accumulation on the matrix cores; FP64 QR, Gram,
+                         eigensolver, scalars; FP32 elementwise pass */
 };
 
 /* Solver configuration.  pasd_config_init() fills every field with its
@@ -102,7 +104,9 @@ typedef struct {
   int eig_sweeps[PASD_MAX_ORDER];   /* Jacobi sweeps of the last Gram eigensolve, per mode */
   double tol_effective;             /* tolerance of the last stopping test: max(tol, 8 u max|T - E|)
                                        with u the unit roundoff of the state (2^-24 in FP32, where
-                                       the N low-rank copies cannot agree beyond a few ulps) */
+                                       the N low-rank copies cannot agree beyond a few ulps;
+                                       2^-11 with BF16 GEMM inputs, i.e. one BF16 unit roundoff of
+                                       max|T - E|, above the measured floor of ~1e-3 max|T - E|) */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;

@@ -305,6 +305,12 @@ __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
     fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk);
 }
 
+// BF16 GEMM inputs: the residual levels off near 1e-3 max|D| (measured on
+// the 200^3, video-shaped and serving workloads, fluctuating up to ~1.3e-3),
+// so u = 2^-11 makes the test certify one BF16 unit roundoff, 8 u = 2^-8, of
+// max|D|.
+constexpr double kBf16Level = 4.8828125e-04;
+
 // One wave: fold the residual slots (and clear them for the next iteration),
 // then lane 0 applies Algorithm 1, lines 7-8.
 template <typename S>
@@ -330,8 +336,12 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
   // each rebuilt from FP32 factors, so they disagree by a few units in the last
   // place of |D|, and the residual T - Z_n - E cannot be certified below that:
   // the test uses max(tol, 8 u max|D|), u the unit roundoff of the state type
-  // (2^-24 for FP32; 2^-53 leaves the FP64 test unchanged in practice).
-  const double u = sizeof(S) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16;
+  // (2^-24 for FP32; 2^-53 leaves the FP64 test unchanged in practice).  With
+  // BF16 GEMM inputs P_n carries the rounding of its operands, and u is the
+  // measured relative level of the disagreement that leaves.
+  const double u = pb.precision == PASD_BF16_GEMM ? kBf16Level
+                   : sizeof(S) == 4               ? 5.9604644775390625e-08
+                                                  : 1.1102230246251565e-16;
   const double dmax = res[pb.N];
   const double tol_eff = pb.tol > 0.0 ? fmax(pb.tol, 8.0 * u * dmax) : 0.0;  // tol 0: never stop
   sc->dmax = dmax;

@@ -52,6 +52,22 @@ __device__ __forceinline__ d4v mma64(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// GEMM operand in the requested input precision: with BF the FP32 value is
+// rounded to the nearest BF16 (ties to even; infinities and NaN unchanged).
+// A product of two BF16 values is exact in FP32, so the FP32 MFMA then
+// computes exactly the BF16-input, FP32-accumulate product.
+template <bool BF, typename S>
+__device__ __forceinline__ S opnd(S x) {
+  if constexpr (BF) {
+    static_assert(sizeof(S) == 4, "BF16 operands come from FP32 state");
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) != 0x7f800000u) u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    return __uint_as_float(u);
+  } else {
+    return x;
+  }
+}
+
 // Four values of G = D + Y * inv_mu at element offsets off[t] (t < nvalid).
 // `contig` means the four offsets are consecutive and 4-aligned.
 template <typename S>
@@ -79,7 +95,7 @@ __device__ __forceinline__ void load_g4(const S* __restrict__ D, const S* __rest
 // one tile since they share the output.
 // ---------------------------------------------------------------------------
 
-template <typename S>
+template <typename S, bool BF>
 __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
@@ -139,7 +155,8 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u[k], d[k][t] + y[k][t] * inv_mu, acc[t]);
+          for (int t = 0; t < 4; ++t)
+            acc[t] = MM<S>::mma(opnd<BF>(u[k]), opnd<BF>(d[k][t] + y[k][t] * inv_mu), acc[t]);
       }
     } else {
       for (int i0 = kbeg; i0 < kend; i0 += 4) {
@@ -154,7 +171,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
           u = Us[(int64_t)i * kRT + p];
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(u, gv[t], acc[t]);
+        for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(opnd<BF>(u), opnd<BF>(gv[t]), acc[t]);
       }
     }
 #pragma unroll
@@ -214,7 +231,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc = MM<S>::mma(rowok ? d[k][t] + y[k][t] * inv_mu : S(0), u[k][t], acc);
+            acc = MM<S>::mma(opnd<BF>(rowok ? d[k][t] + y[k][t] * inv_mu : S(0)), opnd<BF>(u[k][t]), acc);
       }
     } else {
       for (int i0 = 0; i0 < g.I; i0 += 16) {
@@ -230,7 +247,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const S u = (t < nv) ? Us[(int64_t)(i + t) * kRT + p] : S(0);
-          acc = MM<S>::mma(gv[t], u, acc);
+          acc = MM<S>::mma(opnd<BF>(gv[t]), opnd<BF>(u), acc);
         }
       }
     }
@@ -257,7 +274,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 
 constexpr int kMWaves = 8;
 
-template <typename S>
+template <typename S, bool BF>
 __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
   typedef typename MM<S>::vec_t V;
@@ -311,7 +328,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
           const bool ok = (ib0 + u) * 16 + p < g.I;
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc[u] = MM<S>::mma(ok ? dv[u][t] + yv[u][t] * inv_mu : S(0), pvv[t], acc[u]);
+            acc[u] = MM<S>::mma(opnd<BF>(ok ? dv[u][t] + yv[u][t] * inv_mu : S(0)), opnd<BF>(pvv[t]), acc[u]);
         }
       }
       for (; st < send; st += kMWaves) {
@@ -350,7 +367,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
             load_g4<S>(pb.D, mb.Y, o, contig, nvalid, inv_mu, gv);
           }
 #pragma unroll
-          for (int t = 0; t < 4; ++t) acc[u] = MM<S>::mma(gv[t], pv[t], acc[u]);
+          for (int t = 0; t < 4; ++t) acc[u] = MM<S>::mma(opnd<BF>(gv[t]), opnd<BF>(pv[t]), acc[u]);
         }
       }
       // reduce the waves and write rows i = 16(ib0+u) + 4q + v, column r = p
@@ -408,7 +425,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
             const bool ok = (c0 + c) * 64 + 4 * p < g.I;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-              acc[c][t] = MM<S>::mma(ok ? dv[c][t] + yv[c][t] * inv_mu : S(0), pv, acc[c][t]);
+              acc[c][t] = MM<S>::mma(opnd<BF>(ok ? dv[c][t] + yv[c][t] * inv_mu : S(0)), opnd<BF>(pv), acc[c][t]);
           }
         }
       } else {
@@ -429,7 +446,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
               load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[c][t] = MM<S>::mma(gv[t], pv, acc[c][t]);
+            for (int t = 0; t < 4; ++t) acc[c][t] = MM<S>::mma(opnd<BF>(gv[t]), opnd<BF>(pv), acc[c][t]);
           }
         }
       }
@@ -593,18 +610,37 @@ int reduce_m_blocks(const ModeGeom& g) { return (int)(((int64_t)g.I * kRT + 63) 
 template <typename S>
 static int mode_grid(const Problem<S>& p, int kind) { return p.kb[kind][p.N]; }
 
+// A set is homogeneous in precision (the batch driver groups by it); the
+// BF16-input variant exists for the FP32 state only.
+template <typename S>
+static bool bf16_set(const LaunchSet<S>& ls) {
+  return sizeof(S) == 4 && ls.host[0]->precision == PASD_BF16_GEMM;
+}
+
 template <typename S>
 void launch_gemm_p(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_P); });
-  hipLaunchKernelGGL(k_gemm_p<S>, dim3(tot), dim3(256), 0, s, b);
+  if constexpr (sizeof(S) == 4) {
+    if (bf16_set(ls)) {
+      hipLaunchKernelGGL((k_gemm_p<S, true>), dim3(tot), dim3(256), 0, s, b);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm_p<S, false>), dim3(tot), dim3(256), 0, s, b);
 }
 
 template <typename S>
 void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_M); });
-  hipLaunchKernelGGL(k_gemm_m<S>, dim3(tot), dim3(64 * kMWaves), 0, s, b);
+  if constexpr (sizeof(S) == 4) {
+    if (bf16_set(ls)) {
+      hipLaunchKernelGGL((k_gemm_m<S, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_gemm_m<S, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
 }
 
 template <typename S>

@@ -113,8 +113,6 @@ int validate_impl(const pasd_config* c) {
   if (c->max_iter < 1) return fail(PASD_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (c->precision != PASD_FP64 && c->precision != PASD_FP32 && c->precision != PASD_BF16_GEMM)
     return fail(PASD_ERR_INVALID_ARG, "unknown precision");
-  if (c->precision == PASD_BF16_GEMM)
-    return fail(PASD_ERR_UNSUPPORTED, "PASD_BF16_GEMM is not available in this build");
   return PASD_OK;
 }
 
