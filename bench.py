@@ -28,6 +28,27 @@ METRIC = "TRPCA solves/s + ADMM iters/s at rel.err≤1e-5 vs FP64; p50/p99 laten
 HBM_PEAK_GBS = 8000.0
 
 
+def _measured_traffic():
+    """Calibrated HBM bytes per fused-pass launch from the committed counter
+    profile, or None once the kernel source differs from the measured one."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "pasd_c2_fp32_hbm_traffic.md")
+    try:
+        vals = {}
+        for line in open(path):
+            if ":" in line and line.strip().startswith("fused_"):
+                k, v = line.strip().split(":", 1)
+                vals[k.strip()] = v.strip()
+        src = os.path.join(here, vals["fused_source"])
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if digest != vals["fused_source_sha256"]:
+            return None
+        return int(vals["fused_traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -187,8 +208,9 @@ def main():
         kernels[k]["GB/s"] = b / (kernels[k]["ms"] * 1e-3) / 1e9
     dom = max(kb, key=lambda k: kernels[k]["ms"])
     ach = kernels[dom]["GB/s"]
+    traffic = _measured_traffic() if dom == "fused" else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": kb[dom], "ms_per_launch": kernels[dom]["ms"]}
     s.close()
 
@@ -217,7 +239,7 @@ def main():
     # ---- full solves to tol 1e-6: FP32 and FP64 on the same bytes -----------
     if not args.no_solve:
         res = {}
-        for prec, T in (("fp32", T32), ("fp64", T64)):
+        for prec, T in (("fp32", T32), ("fp64", T64), ("bf16", T32)):
             sv = P.Solver(T, ranks, precision=prec, tol=wl.tol, max_iter=wl.max_iter, device=0)
             sv.solve()  # warm-up solve
             sv.reset()
@@ -238,6 +260,9 @@ def main():
                 "iters_per_s": round(r["iters"] / (r["ms"] * 1e-3), 1),
                 "final_residual": r["residual"]} for p, r in res.items()}
         out["solve"]["fp32_vs_fp64_rel_err"] = {"X": ex, "E": ee, "within_1e-5": ex <= 1e-5 and ee <= 1e-5}
+        bx = _rel(res["bf16"]["X"], res["fp64"]["X"])
+        be = _rel(res["bf16"]["E"], res["fp64"]["E"])
+        out["solve"]["bf16_vs_fp64_rel_err"] = {"X": bx, "E": be, "within_1e-5": bx <= 1e-5 and be <= 1e-5}
         out["solve"]["rse_vs_planted_fp64"] = _rel(res["fp64"]["X"], wl.L)
         out["solves_per_s"] = out["solve"]["fp32"]["solves_per_s"]
         _progress("full solves done")
