@@ -235,7 +235,7 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
 // change the stored iterate only through the rounding of mu.  The residual is
 // taken from the stored D.
 template <typename S, int NN, int VEC, int RP, typename IT>
-__device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk) {
+__device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk, bool xcd_split) {
   // Accumulation type of Z_n and type of the elementwise arithmetic.  Both are
   // the state type: wider registers were measured to leave FP32 convergence
   // (iteration counts, converged fraction) unchanged and cost 5-10% here.
@@ -248,7 +248,21 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   const ET theta = (ET)(1.0 / (mu_d * NN));
   const ET invN = (ET)(1.0 / NN);
   AbsMax<ET> rmax[NN + 1];  // residual of every mode, then max |D|
-  for (IT c = (IT)lblk * blockDim.x + threadIdx.x; c < v.nchunk; c += (IT)nblk * blockDim.x) {
+  // Blocks are dealt to the 8 XCDs in turn (block b to XCD b mod 8).  When the
+  // problem's blocks split evenly, the blocks of one XCD sweep (grid-stride)
+  // one contiguous eighth of the tensor: the P_n columns a region needs are
+  // fetched into one XCD's L2 instead of all eight, and each XCD's accesses
+  // stay in one compact front.
+  IT c0 = 0, c1 = v.nchunk, first = (IT)lblk * blockDim.x, step = (IT)nblk * blockDim.x;
+  if (xcd_split) {
+    const IT per = (v.nchunk + kXcds - 1) / kXcds;
+    const int x = lblk % kXcds;
+    c0 = (IT)x * per;
+    c1 = c0 + per < v.nchunk ? c0 + per : v.nchunk;
+    first = (IT)(lblk / kXcds) * blockDim.x;
+    step = (IT)(nblk / kXcds) * blockDim.x;
+  }
+  for (IT c = c0 + first + threadIdx.x; c < c1; c += step) {
     const IT row = div_fixed<IT>(c, v.Q, v.fq);
     const IT i = (c - row * v.Q) * VEC;
     const IT x0 = c * VEC;
@@ -297,12 +311,14 @@ __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
   const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done) return;
-  const int lblk = blockIdx.x - bt.start[req];
-  const int nblk = bt.start[req + 1] - bt.start[req];
+  const int s0 = bt.start[req];
+  const int nblk = bt.start[req + 1] - s0;
+  const int lblk = blockIdx.x - s0;
+  const bool xcd_split = nblk % kXcds == 0 && s0 % kXcds == 0;
   if (pb.vecw)
-    fused_body<S, NN, VW<S>::n, RP, IT>(pb, lblk, nblk);
+    fused_body<S, NN, VW<S>::n, RP, IT>(pb, lblk, nblk, xcd_split);
   else
-    fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk);
+    fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk, xcd_split);
 }
 
 // BF16 GEMM inputs: the residual levels off near 1e-3 max|D| (measured on

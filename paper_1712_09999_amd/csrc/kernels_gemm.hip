@@ -103,7 +103,14 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
   if (pb.sc->done) return;
   const int lb = blockIdx.x - bt.start[req];
   const int n = mode_of(pb.kb[KB_GEMM_P], pb.N, lb);
-  const int64_t tile = lb - pb.kb[KB_GEMM_P][n];
+  int64_t tile = lb - pb.kb[KB_GEMM_P][n];
+  {
+    // Blocks are dealt to the 8 XCDs in turn; give each XCD a contiguous run
+    // of tiles, so that the cache lines two neighbouring tiles share (rows
+    // shorter than a tile's span) are fetched into one L2.
+    const int nt = pb.kb[KB_GEMM_P][n + 1] - pb.kb[KB_GEMM_P][n];
+    tile = xcd_order((int)tile, nt, bt.start[req] + pb.kb[KB_GEMM_P][n]);
+  }
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const S inv_mu = S(1.0 / pb.sc->mu);

@@ -509,12 +509,20 @@ __global__ void __launch_bounds__(64) k_qr_reg(Batch<S> bt) {
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int I = g.I, R = g.R, lane = threadIdx.x;
+  // M rows are kRT doubles (16-byte aligned); every lane issues all of its
+  // 16-byte loads at once (rows past I clamped, then masked with columns >= R)
+  typedef double d2v __attribute__((ext_vector_type(2)));
   double a[TR][RP];
 #pragma unroll
   for (int t = 0; t < TR; ++t) {
     const int i = lane + 64 * t;
+    const double* row = mb.M + (int64_t)(i < I ? i : I - 1) * kRT;
 #pragma unroll
-    for (int c = 0; c < RP; ++c) a[t][c] = (i < I && c < R) ? mb.M[(int64_t)i * kRT + c] : 0.0;
+    for (int c = 0; c < RP; c += 2) {
+      const d2v v = *reinterpret_cast<const d2v*>(row + c);
+      a[t][c] = (i < I && c < R) ? v[0] : 0.0;
+      a[t][c + 1] = (i < I && c + 1 < R) ? v[1] : 0.0;
+    }
   }
   __shared__ double lds[kBatchLds];
   double tau[RP];

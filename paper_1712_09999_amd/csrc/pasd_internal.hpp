@@ -11,6 +11,7 @@ namespace pasd {
 constexpr int kMaxN = PASD_MAX_ORDER;
 constexpr int kRT = 16;        // rank tile: R_n is padded to 16 in the factors and partials
 constexpr int kResSlots = 64;  // residual maxima are spread over this many words per mode
+constexpr int kXcds = 8;       // accelerator complex dies of gfx950; blocks are dealt to them in turn
 
 // Division by a divisor d >= 1 fixed for a whole launch, by multiply-high,
 // add and shift (Granlund and Montgomery, "Division by invariant integers using
@@ -124,6 +125,23 @@ __device__ __forceinline__ int batch_find(const int* start, int nreq, int blk) {
     if (blk >= start[mid]) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// Blocks of a launch are dealt to the XCDs in turn (global block g to XCD
+// g mod kXcds).  For the nt consecutive blocks m0 .. m0 + nt - 1 of one work
+// range, return the position of local block b in an order that lists each
+// XCD's blocks contiguously (XCD 0's first, ...): consecutive positions then
+// run on one XCD and share its L2.  A bijection on [0, nt) for any nt, m0.
+__host__ __device__ inline int xcd_order(int b, int nt, int m0) {
+  const int first_cls = m0 % kXcds;  // class of local block 0
+  const int c = (first_cls + b) % kXcds;
+  int off = 0;
+  for (int y = 0; y < c; ++y) {
+    const int f = (y - first_cls + kXcds) % kXcds;  // first local block of class y
+    off += f < nt ? (nt - f + kXcds - 1) / kXcds : 0;
+  }
+  const int f = (c - first_cls + kXcds) % kXcds;
+  return off + (b - f) / kXcds;
 }
 
 __device__ __forceinline__ int mode_of(const int* kb, int N, int lblk) {

@@ -1,9 +1,14 @@
-// Host check of the fixed-divisor division used by the fused pass: compares
-// fastdiv(n, make_fastdiv(d)) with n / d over divisors 1..4096, every power of
-// two and its neighbours, and large divisors, at numerators near 0, near
-// multiples of d and near 2^31.  Prints the number of mismatches.
+// Host checks of the index helpers of the kernels:
+//  * fastdiv(n, make_fastdiv(d)) against n / d over divisors 1..4096, every
+//    power of two and its neighbours, and large divisors, at numerators near 0,
+//    near multiples of d and near 2^31;
+//  * xcd_order(b, nt, m0) is a bijection on [0, nt) that lists the blocks of
+//    each XCD class ((m0 + b) mod 8) contiguously.
+// Prints the number of mismatches.
 #include <stdint.h>
 #include <stdio.h>
+
+#include <vector>
 
 #include "pasd_internal.hpp"
 
@@ -38,6 +43,22 @@ int main() {
     x ^= x << 13; x ^= x >> 7; x ^= x << 17;
     bad += check((uint32_t)(1 + x % ((uint64_t(1) << 31) - 1)));
   }
+  long obad = 0;
+  for (int nt = 1; nt <= 700; ++nt)
+    for (int m0 = 0; m0 < 24; ++m0) {
+      std::vector<int> seen(nt, 0), at(nt, -1);
+      for (int b = 0; b < nt; ++b) {
+        const int p = pasd::xcd_order(b, nt, m0);
+        if (p < 0 || p >= nt || seen[p]++) { ++obad; continue; }
+        at[p] = b;
+      }
+      int runs = 0;  // class changes along the order: at most kXcds - 1
+      for (int p = 1; p < nt; ++p)
+        if (at[p] >= 0 && at[p - 1] >= 0 &&
+            (m0 + at[p]) % pasd::kXcds != (m0 + at[p - 1]) % pasd::kXcds) ++runs;
+      if (runs > pasd::kXcds - 1) ++obad;
+    }
   printf("divisors %ld mismatches %ld\n", cases, bad);
-  return bad == 0 ? 0 : 1;
+  printf("xcd orders mismatches %ld\n", obad);
+  return bad == 0 && obad == 0 ? 0 : 1;
 }

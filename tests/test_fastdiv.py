@@ -1,9 +1,10 @@
-"""Host check of the fixed-divisor division of the fused pass (no GPU needed).
+"""Host checks of the kernels' index helpers (no GPU needed).
 
 The fused kernel divides element indices by launch-constant divisors with the
 multiply-high/add/shift method of Granlund and Montgomery (1994).  This test
 compiles the library's own header into a host program and compares the
-division with the exact quotient over many divisors and numerators up to 2^31.
+division with the exact quotient over many divisors and numerators up to 2^31,
+and checks that the XCD block order is a bijection grouping each XCD's blocks.
 """
 import os
 import shutil
@@ -22,7 +23,7 @@ def _hipcc():
     return None
 
 
-def test_fastdiv_matches_exact_division(tmp_path):
+def test_index_helpers(tmp_path):
     hipcc = _hipcc()
     if hipcc is None:
         pytest.skip("hipcc not available")
@@ -33,4 +34,5 @@ def test_fastdiv_matches_exact_division(tmp_path):
     assert r.returncode == 0, r.stderr
     out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stdout + out.stderr
-    assert "mismatches 0" in out.stdout
+    assert "divisors" in out.stdout and "mismatches 0\n" in out.stdout
+    assert "xcd orders mismatches 0" in out.stdout
