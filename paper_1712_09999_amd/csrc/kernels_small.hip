@@ -1,4 +1,4 @@
-// Small per-mode FP64 kernels of the PASD iteration, one 64-lane wave per mode.
+// Small per-mode FP64 kernels of the PASD iteration, one block per (problem, mode).
 //
 //   k_qr  : U_n = Q of the Householder QR of M_n = G_n P_n^T.  range(U_n) is the
 //           range of the Procrustes solution of eqs. (9)-(10); the iterates
@@ -142,16 +142,84 @@ __global__ void __launch_bounds__(64) k_qr(Batch<S> bt) {
 //  3. before each sweep the block checks whether any pair still needs a
 //     rotation, so a converged matrix costs one check instead of a sweep;
 //  4. round-robin Jacobi: every round rotates R'/2 disjoint pairs (R' = R
-//     rounded up to even, a dummy index for odd R), one lane per pair, with
-//     the rotation in Rutishauser's form: for x = s_qq - s_pp, y = 2 s_pq,
-//     r = hypot(x, y), w = |x| + r: c = w / hypot(w, y), s = sgn(x) y / hypot(w, y),
-//     t = s / c = sgn(x) y / w;
-//  5. W_f = W diag(f) W^T and U W_f.
+//     rounded up to even, a dummy index for odd R); each thread recomputes
+//     the rotations of the pairs it touches (jacobi_rotation), reads the
+//     matrix from one buffer and writes the other, so a round has one barrier;
+//  5. W_f = W diag(f) W^T and U W_f (FP64 MFMA).
 // A pair is rotated while |s_pq| > thr sqrt(|s_pp s_qq|), thr = 4e-16 for an
-// FP64 state and 1e-10 for FP32, whose factors U W_f are rounded to 2^-24.
+// FP64 state and 1e-10 for FP32, whose factors U W_f are rounded to 2^-24
+// (and |s_pq| > 1e-150, see jacobi_needed).
 // W_f is a spectral function of S, so it does not depend on W0 beyond rounding.
 // ---------------------------------------------------------------------------
 constexpr int kEigParts = 32;  // Gram partials summed in one pass of loads
+
+// Pair idx of round rd of the round-robin (chess tournament) ordering of the
+// indices 0 .. m (m odd): index m stays, the others rotate; p < q.
+__device__ __forceinline__ void rr_pair(int rd, int idx, int m, int& p, int& q) {
+  if (idx == 0) {
+    p = m;
+    q = rd;
+  } else {  // (rd + idx) mod m and (rd - idx) mod m; both operands lie in [0, 2m)
+    p = rd + idx;
+    p = p >= m ? p - m : p;
+    q = rd - idx + m;
+    q = q >= m ? q - m : q;
+  }
+  if (p > q) {
+    const int tmp = p;
+    p = q;
+    q = tmp;
+  }
+}
+
+// 1/sqrt(a) and 1/a for normal a > 0: the hardware estimates (v_rsq_f64,
+// v_rcp_f64, relative error near 2^-23) refined by two Newton steps each,
+// h <- h + h (1 - a h^2) / 2 and r <- r + r (1 - a r), which square the error
+// twice (to the rounding level).  Much shorter dependent chains than the
+// correctly rounded library square root and division.
+__device__ __forceinline__ double rsqrt_nr(double a) {
+  double h = __builtin_amdgcn_rsq(a);
+  h = fma(0.5 * h, fma(-a * h, h, 1.0), h);
+  h = fma(0.5 * h, fma(-a * h, h, 1.0), h);
+  return h;
+}
+__device__ __forceinline__ double rcp_nr(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  r = fma(fma(-a, r, 1.0), r, r);
+  r = fma(fma(-a, r, 1.0), r, r);
+  return r;
+}
+
+// Whether the pair (p, q) of the symmetric A needs a rotation:
+// |a_pq| > thr sqrt(|a_pp a_qq|), compared in squares, and |a_pq| > 1e-150 so
+// that the squares below stay normal.  (A matrix below that scale has every
+// singular value far under the threshold tau: its SVT factor is zero.)
+__device__ __forceinline__ bool jacobi_needed(const double (*A)[kRT + 1], int p, int q, double thr) {
+  const double b = fabs(A[p][q]);
+  return b > 1e-150 && b * b > thr * thr * fabs(A[p][p]) * fabs(A[q][q]);
+}
+
+// Rotation (c, s, t = s / c) that annihilates A[p][q] of the symmetric A, in
+// Rutishauser's form: x = a_qq - a_pp, y = 2 a_pq, r = hypot(x, y), w = |x| + r,
+// c = w / hypot(w, y), s = sgn(x) y / hypot(w, y), t = sgn(x) y / w.  The
+// identity when q is the padding index or the pair is below the threshold.
+__device__ __forceinline__ void jacobi_rotation(const double (*A)[kRT + 1], int p, int q, int R,
+                                                double thr, double& c, double& s, double& t) {
+  c = 1.0;
+  s = 0.0;
+  t = 0.0;
+  if (q < R && jacobi_needed(A, p, q, thr)) {
+    const double x = A[q][q] - A[p][p], y = 2.0 * A[p][q];
+    const double n1 = fma(x, x, y * y);
+    const double r = n1 * rsqrt_nr(n1);
+    const double w = fabs(x) + r;
+    const double sy = x >= 0.0 ? y : -y;
+    const double h = rsqrt_nr(fma(w, w, y * y));
+    c = w * h;
+    s = sy * h;
+    t = sy * rcp_nr(w);
+  }
+}
 
 template <typename S>
 __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
@@ -163,31 +231,41 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   const ModeBufs<S> mb = pb.m[n];
   const int R = g.R, I = g.I, tid = threadIdx.x;
   const bool warm = pb.sc->k > 0;
-  __shared__ double Sm[kRT][kRT + 1];
+  __shared__ double Sb[2][kRT][kRT + 1];  // the Gram in two buffers (Jacobi rounds alternate)
   __shared__ double W[kRT][kRT + 1];
   __shared__ double T1[kRT][kRT + 1];
-  __shared__ double rot[kRT / 2][3];  // c, s, t of each pair of the round
-  __shared__ int pq[kRT / 2][2];
   __shared__ double fac[kRT];
   __shared__ double Ul[kQrLds];
+  double (*Sm)[kRT + 1] = Sb[0];
   {
     const int r = tid / kRT, c = tid % kRT;
     const bool in = r < R && c < R;
     // all loads of this thread first: its share of U_n, then the partials
+    // Loads are unconditional (indices clamped into range, values masked
+    // afterwards): a load under a condition is compiled as a branch with a
+    // wait after it, which serialises the round trips.
     constexpr int kU = 8;
+    const int nU = I * R;
     double uv[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int e = tid + 256 * u;
-      uv[u] = e < I * R ? mb.U[e] : 0.0;
+      uv[u] = mb.U[e < nU ? e : nU - 1];
     }
     const int nb = mb.sblocks;
     const double* sp = mb.Spart + tid;
     double part[kEigParts];
 #pragma unroll
-    for (int b = 0; b < kEigParts; ++b) part[b] = (in && b < nb) ? sp[(int64_t)b * kRT * kRT] : 0.0;
-    for (int b = kEigParts; b < nb; ++b)
-      if (in) part[b % kEigParts] += sp[(int64_t)b * kRT * kRT];
+    for (int b = 0; b < kEigParts; ++b) part[b] = 0.0;
+    // kEigParts partials per pass, static register indices (no private memory)
+    for (int b0 = 0; b0 < nb; b0 += kEigParts) {
+      double v[kEigParts];
+#pragma unroll
+      for (int b = 0; b < kEigParts; ++b) v[b] = sp[(int64_t)(b0 + b < nb ? b0 + b : nb - 1) * kRT * kRT];
+#pragma unroll
+      for (int b = 0; b < kEigParts; ++b)
+        if (in && b0 + b < nb) part[b] += v[b];
+    }
     // fixed-order pairwise sum of the partials
 #pragma unroll
     for (int w = kEigParts / 2; w > 0; w /= 2)
@@ -198,7 +276,7 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int e = tid + 256 * u;
-      if (e < I * R) Ul[e] = uv[u];
+      if (e < nU) Ul[e] = uv[u];
     }
     for (int e = tid + 256 * kU; e < I * R; e += 256) Ul[e] = mb.U[e];
   }
@@ -224,60 +302,31 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   const int half = Rp / 2;
   const int m = Rp - 1;
   int sweeps = 0;
+  int cur = 0;  // Sb[cur] holds the current matrix
   for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
     int need = 0;
     {
       const int p = tid / kRT, q = tid % kRT;
-      if (p < q && q < R) {
-        const double b = fabs(Sm[p][q]);
-        need = b > 1e-300 && b > thr * sqrt(fabs(Sm[p][p])) * sqrt(fabs(Sm[q][q]));
-      }
+      if (p < q && q < R) need = jacobi_needed(Sb[cur], p, q, thr);
     }
     if (!__syncthreads_or(need)) break;
     sweeps = sweep + 1;
     for (int rd = 0; rd < m; ++rd) {
-      if (tid < half) {
-        int p, q;
-        if (tid == 0) {
-          p = m;
-          q = rd;
-        } else {
-          p = (rd + tid) % m;
-          q = (rd - tid + m) % m;
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (q < R) {
-          const double a = Sm[p][p], d = Sm[q][q], b = Sm[p][q];
-          const double ab = fabs(b);
-          if (ab > 1e-300 && ab > thr * sqrt(fabs(a)) * sqrt(fabs(d))) {
-            const double x = d - a, y = 2.0 * b;
-            const double r = sqrt(x * x + y * y);
-            const double w = fabs(x) + r;
-            const double sy = x >= 0.0 ? y : -y;
-            const double h = 1.0 / sqrt(w * w + y * y);
-            c = w * h;
-            s = sy * h;
-            t = sy / w;
-          }
-        }
-        rot[tid][0] = c;
-        rot[tid][1] = s;
-        rot[tid][2] = t;
-        pq[tid][0] = p;
-        pq[tid][1] = q;
-      }
-      __syncthreads();
+      // Every thread derives the pairs and rotations it needs from the round
+      // number and the current matrix, so a round is one read of Sb[cur], one
+      // write of every entry of the other buffer, and one barrier.
+      const double (*A)[kRT + 1] = Sb[cur];
+      double (*B)[kRT + 1] = Sb[cur ^ 1];
       if (tid < half * half) {
         const int k = tid / half, l = tid - k * half;
         if (k <= l) {
-          const int pk = pq[k][0], qk = pq[k][1], pl = pq[l][0], ql = pq[l][1];
-          const double ck = rot[k][0], sk = rot[k][1], cl = rot[l][0], sl = rot[l][1];
-          const double x00 = Sm[pk][pl], x01 = Sm[pk][ql], x10 = Sm[qk][pl], x11 = Sm[qk][ql];
+          int pk, qk, pl, ql;
+          rr_pair(rd, k, m, pk, qk);
+          rr_pair(rd, l, m, pl, ql);
+          double ck, sk, tk, cl, sl, tl;
+          jacobi_rotation(A, pk, qk, R, thr, ck, sk, tk);
+          jacobi_rotation(A, pl, ql, R, thr, cl, sl, tl);
+          const double x00 = A[pk][pl], x01 = A[pk][ql], x10 = A[qk][pl], x11 = A[qk][ql];
           // rows: J_k^T
           const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
           const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
@@ -286,32 +335,35 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
           double z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
           if (k == l && sk != 0.0) {
             // diagonal block: the rotation annihilates the off-diagonal entry
-            const double tb = rot[k][2] * x01;
+            const double tb = tk * x01;
             z00 = x00 - tb;
             z11 = x11 + tb;
             z01 = 0.0;
             z10 = 0.0;
           }
           // blocks (k, l) and (l, k) are mirror images: write both from one lane
-          Sm[pk][pl] = z00;
-          Sm[pk][ql] = z01;
-          Sm[qk][pl] = z10;
-          Sm[qk][ql] = z11;
-          Sm[pl][pk] = z00;
-          Sm[ql][pk] = z01;
-          Sm[pl][qk] = z10;
-          Sm[ql][qk] = z11;
+          B[pk][pl] = z00;
+          B[pk][ql] = z01;
+          B[qk][pl] = z10;
+          B[qk][ql] = z11;
+          B[pl][pk] = z00;
+          B[ql][pk] = z01;
+          B[pl][qk] = z10;
+          B[ql][qk] = z11;
         }
       } else if (tid >= 64 && tid < 64 + R * half) {
         const int t = tid - 64;
         const int i = t / half, l = t - (t / half) * half;
-        const int pl = pq[l][0], ql = pq[l][1];
-        const double cl = rot[l][0], sl = rot[l][1];
+        int pl, ql;
+        rr_pair(rd, l, m, pl, ql);
+        double cl, sl, tl;
+        jacobi_rotation(A, pl, ql, R, thr, cl, sl, tl);
         const double wp = W[i][pl], wq = W[i][ql];
         W[i][pl] = cl * wp - sl * wq;
         W[i][ql] = sl * wp + cl * wq;
       }
       __syncthreads();
+      cur ^= 1;
     }
   }
   if (tid == 0) pb.sc->eig_sweeps[n] = sweeps;
@@ -319,7 +371,7 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   if (tid < kRT) {
     double f = 0.0;
     if (tid < R) {
-      const double l = Sm[tid][tid];
+      const double l = Sb[cur][tid][tid];
       const double sig = sqrt(l > 0.0 ? l : 0.0);
       f = sig > tau ? (sig - tau) / sig : 0.0;
     }
@@ -340,31 +392,35 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
     mb.Wev[tid] = (r < R && c < R) ? W[r][c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  // U W_f: thread (c, i0) = (tid % 16, tid / 16) forms column c of rows
-  // i0, i0 + 16, ... with column c of W_f in registers, four rows at a time
+  // U W_f on the FP64 matrix cores: row block rb (16 rows of U) times W_f
+  // (R x 16, zero beyond R), K = 16 in steps of 4; wave w takes blocks w,
+  // w + 4, ...  Lane l supplies A[l%16][k] = U[16 rb + l%16][4 s + l/16] and
+  // B[k][l%16] = W_f[4 s + l/16][l%16], and ends with rows 4 v + l/16 of
+  // column l%16 (the FP64 result layout).
   {
-    const int c = tid % kRT;
-    double wf[kRT];
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    const int lane = tid & 63, wave = tid >> 6;
+    const int p = lane & 15, q = lane >> 4;
+    const int nrb = (I + 15) / 16;
+    double wfb[kRT / 4];
 #pragma unroll
-    for (int r = 0; r < kRT; ++r) wf[r] = T1[r][c];
-    for (int i0 = tid / kRT; i0 < I; i0 += 4 * (256 / kRT)) {
-      // fully unrolled over the 16 rank slots (W_f is zero beyond R, the
-      // U reads are masked) so that wf stays in fixed registers
-      double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int st = 0; st < kRT / 4; ++st) wfb[st] = T1[4 * st + q][p];
+    for (int rb = wave; rb < nrb; rb += 4) {
+      const int row = 16 * rb + p;
+      const int rc = row < I ? row : I - 1;
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int r = 0; r < kRT; ++r) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = min(i0 + u * (256 / kRT), I - 1);
-          s[u] += (r < R ? Ul[i * R + r] : 0.0) * wf[r];
-        }
+      for (int st = 0; st < kRT / 4; ++st) {
+        const int k = 4 * st + q;
+        const double av = Ul[rc * R + (k < R ? k : 0)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((row < I && k < R) ? av : 0.0, wfb[st], acc, 0, 0, 0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + u * (256 / kRT);
-        if (i < I) {
-          mb.Uf[(int64_t)i * kRT + c] = (S)s[u];
-          mb.UfT[(int64_t)c * I + i] = (S)s[u];
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * rb + 4 * v + q;
+        if (r < I) {
+          mb.Uf[(int64_t)r * kRT + p] = (S)acc[v];
+          mb.UfT[(int64_t)p * I + r] = (S)acc[v];
         }
       }
     }
