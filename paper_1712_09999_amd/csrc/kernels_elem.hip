@@ -334,20 +334,28 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
   const Problem<S>& pb = *bt.p[blockIdx.x];
   DevScalars* sc = pb.sc;
   if (sc->done) return;
+  __shared__ double res_row[kMaxN + 1];  // folded slot rows; row kMaxN is max |D|
   __shared__ double res[kMaxN + 1];
   const int lane = threadIdx.x;
-  for (int n = 0; n <= pb.N; ++n) {
-    const int row = n < pb.N ? n : kMaxN;  // the last row folded is max |D|
-    unsigned long long b = sc->res_slots[row][lane];
-    sc->res_slots[row][lane] = 0ull;
+  // every row's slots are read before any is cleared, so the loads overlap
+  unsigned long long b[kMaxN + 1];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const unsigned long long other = __shfl_xor(b, o, 64);
-      b = other > b ? other : b;
+  for (int r = 0; r <= kMaxN; ++r) b[r] = sc->res_slots[r][lane];
+#pragma unroll
+  for (int r = 0; r <= kMaxN; ++r) sc->res_slots[r][lane] = 0ull;
+#pragma unroll
+  for (int r = 0; r <= kMaxN; ++r) {
+    if (r < pb.N || r == kMaxN) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(b[r], o, 64);
+        b[r] = other > b[r] ? other : b[r];
+      }
+      if (lane == 0) res_row[r] = __longlong_as_double((long long)b[r]);
     }
-    if (lane == 0) res[n] = __longlong_as_double((long long)b);
   }
   if (lane != 0) return;
+  for (int n = 0; n <= pb.N; ++n) res[n] = res_row[n < pb.N ? n : kMaxN];
   // Stopping test of Algorithm 1 (line 8).  In FP32 state the N copies Z_n are
   // each rebuilt from FP32 factors, so they disagree by a few units in the last
   // place of |D|, and the residual T - Z_n - E cannot be certified below that:

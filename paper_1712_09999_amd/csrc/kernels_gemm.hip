@@ -498,14 +498,23 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   __shared__ double part[4][64];
   double acc[4] = {0, 0, 0, 0};
   if (e < ne) {
+    // group grp sums partials grp, grp + 4, ... into acc[(b / 4) % 4]; kRM
+    // unconditional loads per pass (index clamped, value masked) are in
+    // flight together
+    constexpr int kRM = 24;
     const double* src = mb.Mpart + e;
     const int nb = mb.mblocks;
-    int b = grp;
-    for (; b + 12 < nb; b += 16) {
+    for (int b0 = grp; b0 < nb; b0 += 4 * kRM) {
+      double v[kRM];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += src[(int64_t)(b + 4 * u) * ne];
+      for (int u = 0; u < kRM; ++u) {
+        const int b = b0 + 4 * u;
+        v[u] = src[(int64_t)(b < nb ? b : nb - 1) * ne];
+      }
+#pragma unroll
+      for (int u = 0; u < kRM; ++u)
+        if (b0 + 4 * u < nb) acc[u % 4] += v[u];
     }
-    for (; b < nb; b += 4) acc[0] += src[(int64_t)b * ne];
   }
   part[grp][l] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
