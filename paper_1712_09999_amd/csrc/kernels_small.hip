@@ -143,8 +143,9 @@ __global__ void __launch_bounds__(64) k_qr(Batch<S> bt) {
 //     rotation, so a converged matrix costs one check instead of a sweep;
 //  4. round-robin Jacobi: every round rotates R'/2 disjoint pairs (R' = R
 //     rounded up to even, a dummy index for odd R); each thread recomputes
-//     the rotations of the pairs it touches (jacobi_rotation), reads the
-//     matrix from one buffer and writes the other, so a round has one barrier;
+//     the rotations of the pairs it touches (jacobi_rotation, branch-free),
+//     issues all of its reads first, reads the matrix from one buffer and
+//     writes the other, so a round has one barrier;
 //  5. W_f = W diag(f) W^T and U W_f (FP64 MFMA).
 // A pair is rotated while |s_pq| > thr sqrt(|s_pp s_qq|), thr = 4e-16 for an
 // FP64 state and 1e-10 for FP32, whose factors U W_f are rounded to 2^-24
@@ -199,26 +200,26 @@ __device__ __forceinline__ bool jacobi_needed(const double (*A)[kRT + 1], int p,
   return b > 1e-150 && b * b > thr * thr * fabs(A[p][p]) * fabs(A[q][q]);
 }
 
-// Rotation (c, s, t = s / c) that annihilates A[p][q] of the symmetric A, in
-// Rutishauser's form: x = a_qq - a_pp, y = 2 a_pq, r = hypot(x, y), w = |x| + r,
-// c = w / hypot(w, y), s = sgn(x) y / hypot(w, y), t = sgn(x) y / w.  The
-// identity when q is the padding index or the pair is below the threshold.
-__device__ __forceinline__ void jacobi_rotation(const double (*A)[kRT + 1], int p, int q, int R,
-                                                double thr, double& c, double& s, double& t) {
-  c = 1.0;
-  s = 0.0;
-  t = 0.0;
-  if (q < R && jacobi_needed(A, p, q, thr)) {
-    const double x = A[q][q] - A[p][p], y = 2.0 * A[p][q];
-    const double n1 = fma(x, x, y * y);
-    const double r = n1 * rsqrt_nr(n1);
-    const double w = fabs(x) + r;
-    const double sy = x >= 0.0 ? y : -y;
-    const double h = rsqrt_nr(fma(w, w, y * y));
-    c = w * h;
-    s = sy * h;
-    t = sy * rcp_nr(w);
-  }
+// Rotation (c, s, t = s / c) that annihilates the off-diagonal b of the
+// symmetric 2x2 block [[a, b], [b, d]], in Rutishauser's form:
+// x = d - a, y = 2 b, r = hypot(x, y), w = |x| + r, c = w / hypot(w, y),
+// s = sgn(x) y / hypot(w, y), t = sgn(x) y / w.  The identity when !valid (the
+// padding index) or below the threshold.  Branch-free (the result is selected
+// at the end; a discarded lane may compute with infinities), so that the loads
+// and the arithmetic of several rotations overlap.
+__device__ __forceinline__ void jacobi_rotation(double a, double d, double b, bool valid, double thr,
+                                                double& c, double& s, double& t) {
+  const double ab = fabs(b);
+  const bool need = valid && ab > 1e-150 && ab * ab > thr * thr * fabs(a) * fabs(d);
+  const double x = d - a, y = 2.0 * b;
+  const double n1 = fma(x, x, y * y);
+  const double r = n1 * rsqrt_nr(n1);
+  const double w = fabs(x) + r;
+  const double sy = x >= 0.0 ? y : -y;
+  const double h = rsqrt_nr(fma(w, w, y * y));
+  c = need ? w * h : 1.0;
+  s = need ? sy * h : 0.0;
+  t = need ? sy * rcp_nr(w) : 0.0;
 }
 
 template <typename S>
@@ -323,10 +324,13 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
           int pk, qk, pl, ql;
           rr_pair(rd, k, m, pk, qk);
           rr_pair(rd, l, m, pl, ql);
-          double ck, sk, tk, cl, sl, tl;
-          jacobi_rotation(A, pk, qk, R, thr, ck, sk, tk);
-          jacobi_rotation(A, pl, ql, R, thr, cl, sl, tl);
+          // every read of the round first, then the arithmetic
+          const double akk = A[pk][pk], dkk = A[qk][qk], bk = A[pk][qk];
+          const double all = A[pl][pl], dll = A[ql][ql], bl = A[pl][ql];
           const double x00 = A[pk][pl], x01 = A[pk][ql], x10 = A[qk][pl], x11 = A[qk][ql];
+          double ck, sk, tk, cl, sl, tl;
+          jacobi_rotation(akk, dkk, bk, qk < R, thr, ck, sk, tk);
+          jacobi_rotation(all, dll, bl, ql < R, thr, cl, sl, tl);
           // rows: J_k^T
           const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
           const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
@@ -356,9 +360,10 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
         const int i = t / half, l = t - (t / half) * half;
         int pl, ql;
         rr_pair(rd, l, m, pl, ql);
-        double cl, sl, tl;
-        jacobi_rotation(A, pl, ql, R, thr, cl, sl, tl);
+        const double all = A[pl][pl], dll = A[ql][ql], bl = A[pl][ql];
         const double wp = W[i][pl], wq = W[i][ql];
+        double cl, sl, tl;
+        jacobi_rotation(all, dll, bl, ql < R, thr, cl, sl, tl);
         W[i][pl] = cl * wp - sl * wq;
         W[i][ql] = sl * wp + cl * wq;
       }
@@ -493,9 +498,12 @@ __device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)
       const double alpha = row[0];
       double tc = 0, beta = alpha, scale = 0;
       if (xnorm2 > 0) {
-        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-        tc = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
+        // beta = -sgn(alpha) |(alpha, x)|, tau = (beta - alpha) / beta,
+        // scale = 1 / (alpha - beta); alpha - beta and beta are nonzero here
+        const double n2 = fma(alpha, alpha, xnorm2);
+        beta = -copysign(n2 * rsqrt_nr(n2), alpha);
+        tc = (beta - alpha) * rcp_nr(beta);
+        scale = rcp_nr(alpha - beta);
       }
 #pragma unroll
       for (int t = 0; t < TR; ++t) {
