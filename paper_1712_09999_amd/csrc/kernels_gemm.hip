@@ -612,7 +612,7 @@ int gemm_m_blocks(const ModeGeom& g) {
 
 int gram_blocks(const ModeGeom& g) {
   const int64_t steps = (g.J + 15) / 16;
-  int64_t want = 32;
+  int64_t want = 64;
   int64_t maxb = (steps + 3) / 4;
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }
