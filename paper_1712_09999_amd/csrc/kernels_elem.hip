@@ -214,9 +214,11 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
     const IT in = q1 - a * v.I[n];
     const IT j = a * v.B[n] + (row - q1 * v.Rb[n]) * v.IN + i;
     constexpr int W = VW<S>::n;  // U_n W_n rows are kRT long and 16-byte aligned
-    S u[RP];
+    // U_n W_f rows are kRT wide and zero beyond R: read whole 16-byte vectors
+    constexpr int RU = (RP + W - 1) / W * W;
+    S u[RU];
 #pragma unroll
-    for (int r = 0; r < RP; r += W) gload<S, W, IT>(v.F[n], in * (IT)kRT + (IT)r, &u[r]);
+    for (int r = 0; r < RU; r += W) gload<S, W, IT>(v.F[n], in * (IT)kRT + (IT)r, &u[r]);
     S pv[RP][VEC];
 #pragma unroll
     for (int r = 0; r < RP; ++r) gload<S, VEC, IT>(v.P[n], (IT)r * v.J[n] + j, pv[r]);
@@ -474,20 +476,36 @@ static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {
     hipLaunchKernelGGL((k_fused<S, NN, kRT, uint64_t>), dim3(grid), dim3(256), 0, s, b);
 }
 
-// The rank loop is unrolled to the largest R_n of the set rounded up to 4.
+// The rank loop is unrolled to the largest R_n of the set, rounded up to even
+// for orders up to 4 and to a multiple of 4 above.
 template <typename S, int NN>
 static void fused_n(const LaunchSet<S>& ls, hipStream_t s) {
   int rmax = 1;
   for (int r = 0; r < ls.count; ++r)
     for (int n = 0; n < ls.host[r]->N; ++n) rmax = std::max(rmax, ls.host[r]->g[n].R);
-  if (rmax <= 4)
-    fused_idx<S, NN, 4>(ls, s);
-  else if (rmax <= 8)
-    fused_idx<S, NN, 8>(ls, s);
-  else if (rmax <= 12)
-    fused_idx<S, NN, 12>(ls, s);
-  else
-    fused_idx<S, NN, 16>(ls, s);
+  if constexpr (NN <= 4) {
+    // orders up to 4: the rank loop is unrolled to R rounded up to even (the
+    // pass is bound by its load instructions, one per rank and mode)
+    switch ((rmax + 1) / 2) {
+      case 1: fused_idx<S, NN, 2>(ls, s); return;
+      case 2: fused_idx<S, NN, 4>(ls, s); return;
+      case 3: fused_idx<S, NN, 6>(ls, s); return;
+      case 4: fused_idx<S, NN, 8>(ls, s); return;
+      case 5: fused_idx<S, NN, 10>(ls, s); return;
+      case 6: fused_idx<S, NN, 12>(ls, s); return;
+      case 7: fused_idx<S, NN, 14>(ls, s); return;
+      default: fused_idx<S, NN, 16>(ls, s); return;
+    }
+  } else {
+    if (rmax <= 4)
+      fused_idx<S, NN, 4>(ls, s);
+    else if (rmax <= 8)
+      fused_idx<S, NN, 8>(ls, s);
+    else if (rmax <= 12)
+      fused_idx<S, NN, 12>(ls, s);
+    else
+      fused_idx<S, NN, 16>(ls, s);
+  }
 }
 
 // All problems of a set have the same order N (the batch driver groups them).
