@@ -26,6 +26,15 @@ namespace pasd {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 
+// Loads of the streaming loops go through explicitly global pointers: generic
+// "flat" loads also occupy the LDS wait counter, so every wait for them would
+// drain LDS traffic too.
+#define PASD_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gld(const void* p) {
+  return *(const PASD_GLOBAL T*)p;
+}
+
 template <typename S> struct MM;
 // Operand layout of both 16x16x4 instructions: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16].  Result element v of lane l is D[row(l / 16, v)][l % 16]
@@ -308,30 +317,38 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
     const bool contig = (g.B % 4) == 0;
     const bool pvec = (g.J % 4) == 0;
     const int nib = (g.I + 15) / 16;
+    const int pr = min(p, g.R - 1);  // lanes p >= R read row R-1 (cached) and mask it
     for (int ib0 = 0; ib0 < nib; ib0 += IBP) {
       Acc acc[IBP];
 #pragma unroll
       for (int u = 0; u < IBP; ++u) acc[u] = Acc{0, 0, 0, 0};
       // steps whose 16 columns are all valid, on 4-aligned contiguous columns:
-      // unconditional vector loads (rows past I clamped and masked; P_n has
-      // zero rows up to 16), so that the loads of all row blocks overlap
+      // unconditional vector loads (rows past I and P_n rows past R clamped
+      // and masked), so that the loads of all row blocks overlap
       const int64_t full_end = (contig && pvec) ? min(send, g.J / 16) : sbeg;
+      const bool j32 = g.J < (int64_t(1) << 31);
+      const FastDiv fdb = pb.fd_b[n];
       int64_t st = sbeg + wave;
       for (; st < full_end; st += kMWaves) {
         const int64_t j4 = st * 16 + 4 * q;
-        const int64_t a = j4 / g.B, b = j4 - a * g.B;
-        const int64_t base = a * (int64_t)g.I * g.B + b;
-        const V pvv = *reinterpret_cast<const V*>(mb.P + (int64_t)p * g.J + j4);
+        const int64_t a = j32 ? (int64_t)fastdiv((uint32_t)j4, fdb) : j4 / g.B;
+        const int64_t b = j4 - a * g.B;
+        const S* dp = pb.D + a * (int64_t)g.I * g.B + b;
+        const S* yp = mb.Y + a * (int64_t)g.I * g.B + b;
+        const V pv0 = gld<V>(mb.P + (int64_t)pr * g.J + j4);
         V dv[IBP], yv[IBP];
 #pragma unroll
         for (int u = 0; u < IBP; ++u) {
-          const int i = min((ib0 + u) * 16 + p, g.I - 1);
-          dv[u] = *reinterpret_cast<const V*>(pb.D + base + (int64_t)i * g.B);
-          yv[u] = *reinterpret_cast<const V*>(mb.Y + base + (int64_t)i * g.B);
+          const int64_t i = min((ib0 + u) * 16 + p, g.I - 1);
+          dv[u] = gld<V>(dp + i * g.B);
+          yv[u] = gld<V>(yp + i * g.B);
         }
+        // every load of the step is in flight before the first use
+        __builtin_amdgcn_sched_barrier(0);
+        const V pvv = p < g.R ? pv0 : V{0, 0, 0, 0};
 #pragma unroll
         for (int u = 0; u < IBP; ++u) {
-          if (ib0 + u >= nib) break;
+          // row blocks past I (the last pass) compute on zeros, no branch
           const bool ok = (ib0 + u) * 16 + p < g.I;
 #pragma unroll
           for (int t = 0; t < 4; ++t)
@@ -411,24 +428,25 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
         for (int t = 0; t < 4; ++t) acc[c][t] = Acc{0, 0, 0, 0};
       if (contig) {
         // unconditional loads: row a clamped to A-1, chunk start clamped to
-        // I-4, both masked (P_n has zero rows up to 16)
-#pragma unroll 2
+        // I-4, P_n row clamped to R-1, all masked
         for (int64_t st = sbeg + wave; st < send; st += kMWaves) {
           const int64_t a = st * 4 + q;
           const bool aok = a < g.A;
           const int64_t ac = aok ? a : g.A - 1;
-          const S pv0 = mb.P[(int64_t)p * g.J + ac];
-          const S pv = aok ? pv0 : S(0);
-          V dv[4], yv[4];
+          const S pv0 = gld<S>(mb.P + (int64_t)min(p, g.R - 1) * g.J + ac);
+          V dv[CHP], yv[CHP];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
+          for (int c = 0; c < CHP; ++c) {
             const int i = min((c0 + c) * 64 + 4 * p, g.I - 4);
-            dv[c] = *reinterpret_cast<const V*>(pb.D + ac * g.I + i);
-            yv[c] = *reinterpret_cast<const V*>(mb.Y + ac * g.I + i);
+            dv[c] = gld<V>(pb.D + ac * g.I + i);
+            yv[c] = gld<V>(mb.Y + ac * g.I + i);
           }
+          // every load of the step is in flight before the first use
+          __builtin_amdgcn_sched_barrier(0);
+          const S pv = (aok && p < g.R) ? pv0 : S(0);
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            if (c >= CHP || c0 + c >= nch) break;
+          for (int c = 0; c < CHP; ++c) {
+            // chunks past I (the last pass) compute on zeros, no branch
             const bool ok = (c0 + c) * 64 + 4 * p < g.I;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
@@ -545,12 +563,13 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
   const int64_t send = min(nsteps, sbeg + per_blk);
   const bool pvec = (g.J % 4) == 0;
   d4v acc = d4v{0, 0, 0, 0};
-  // full 16-column steps: unconditional vector loads of row p (rows R..15 of
-  // P_n are zero), kGramU steps of this wave per pass with all their loads
+  // full 16-column steps: unconditional vector loads of row p, kGramU steps of this wave per pass with all their loads
   // issued before the first MFMA
   constexpr int kGramU = 8;
   const int64_t full_end = pvec ? min(send, g.J / 16) : sbeg;
-  const S* prow = mb.P + (int64_t)p * g.J + 4 * q;
+  // (lanes p >= R read row R-1, in cache anyway, and use zero)
+  const bool pok = p < g.R;
+  const S* prow = mb.P + (int64_t)min(p, g.R - 1) * g.J + 4 * q;
   int64_t st = sbeg + wave;
   for (; st + 4 * (kGramU - 1) < full_end; st += 4 * kGramU) {
     V v[kGramU];
@@ -560,12 +579,18 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
 #pragma unroll
     for (int u = 0; u < kGramU; ++u)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc = mma64((double)v[u][t], (double)v[u][t], acc);
+      for (int t = 0; t < 4; ++t) {
+        const double x = pok ? (double)v[u][t] : 0.0;
+        acc = mma64(x, x, acc);
+      }
   }
   for (; st < full_end; st += 4) {
     const V v = *reinterpret_cast<const V*>(prow + st * 16);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc = mma64((double)v[t], (double)v[t], acc);
+    for (int t = 0; t < 4; ++t) {
+      const double x = pok ? (double)v[t] : 0.0;
+      acc = mma64(x, x, acc);
+    }
   }
   for (; st < send; st += 4) {
     const int64_t j4 = st * 16 + 4 * q;
@@ -601,12 +626,12 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
 // Host launchers
 // ---------------------------------------------------------------------------
 
-int gemm_m_blocks(const ModeGeom& g) {
-  // enough blocks of 8 waves to keep ~3 waves per CU busy across all modes,
-  // capped by the available K-steps.
+int gemm_m_blocks(const ModeGeom& g, int N) {
+  // one block of 8 waves per compute unit across the N modes of a solve (a
+  // block holds its CU's register file), capped by the available K-steps
   const int64_t steps = g.B > 1 ? (g.J + 15) / 16 : (g.A + 3) / 4;
-  int64_t want = 96;
-  int64_t maxb = (steps + kMWaves - 1) / kMWaves;
+  const int64_t want = std::max(16, kCUs / std::max(1, N));
+  const int64_t maxb = (steps + kMWaves - 1) / kMWaves;
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }
 

@@ -12,6 +12,7 @@ constexpr int kMaxN = PASD_MAX_ORDER;
 constexpr int kRT = 16;        // rank tile: R_n is padded to 16 in the factors and partials
 constexpr int kResSlots = 64;  // residual maxima are spread over this many words per mode
 constexpr int kXcds = 8;       // accelerator complex dies of gfx950; blocks are dealt to them in turn
+constexpr int kCUs = 256;      // compute units of the MI355X
 
 // Division by a divisor d >= 1 fixed for a whole launch, by multiply-high,
 // add and shift (Granlund and Montgomery, "Division by invariant integers using
@@ -105,6 +106,8 @@ struct Problem {
   FastDiv fd_q;
   FastDiv fd_rb[kMaxN];
   FastDiv fd_i[kMaxN];
+  // unfolding GEMMs: B_n, for column indices j < 2^31
+  FastDiv fd_b[kMaxN];
 };
 
 // One launch over up to kMaxBatch problems (kernel arguments, ~1.6 KB): block
@@ -175,7 +178,7 @@ template <typename S> void launch_output(const Problem<S>& p, S* X, S* E, hipStr
 template <typename S> void launch_component(const Problem<S>& p, int n, S* Z, hipStream_t s);
 
 // Grid sizes chosen on the host.
-int gemm_m_blocks(const ModeGeom& g);
+int gemm_m_blocks(const ModeGeom& g, int N);
 int gram_blocks(const ModeGeom& g);
 int gemm_p_blocks(const ModeGeom& g);
 int reduce_m_blocks(const ModeGeom& g);

@@ -142,7 +142,7 @@ void make_plan(const pasd_config* c, Plan& p) {
     g.I = (int)c->dims[n];
     g.J = g.A * g.B;
     g.R = (int)c->ranks[n];
-    p.mblocks[n] = gemm_m_blocks(g);
+    p.mblocks[n] = gemm_m_blocks(g, N);
     p.sblocks[n] = gram_blocks(g);
   }
   p.off_T = p.L.add(numel * es);
@@ -224,6 +224,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     const bool inner = n < ctx->N - 1 && p.idx32;
     p.fd_rb[n] = make_fastdiv((uint32_t)(inner ? p.g[n].B / IN : 1));
     p.fd_i[n] = make_fastdiv((uint32_t)(inner ? p.g[n].I : 1));
+    p.fd_b[n] = make_fastdiv((uint32_t)(n < ctx->N && p.g[n].B < (int64_t(1) << 31) ? p.g[n].B : 1));
   }
 }
 
