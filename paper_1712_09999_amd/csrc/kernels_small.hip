@@ -1,9 +1,11 @@
 // Small per-mode FP64 kernels of the PASD iteration, one block per (problem, mode).
 //
-//   k_qr  : U_n = Q of the Householder QR of M_n = G_n P_n^T.  range(U_n) is the
-//           range of the Procrustes solution of eqs. (9)-(10); the iterates
+//   k_qr* : U_n = an orthonormal basis of range(M_n), M_n = G_n P_n^T, which is
+//           the range of the Procrustes solution of eqs. (9)-(10); the iterates
 //           depend on range(U_n) only, so any orthonormal basis of it will do.
-//           Householder QR stays orthonormal when M_n is rank deficient.
+//           CholeskyQR2 on the matrix cores where M_n is well conditioned,
+//           Householder QR otherwise (it stays orthonormal when M_n is rank
+//           deficient).
 //   k_eig : S_n = P_n P_n^T = W diag(l) W^T by parallel cyclic Jacobi; with
 //           s_i = sqrt(l_i) (the singular values of P_n) and tau = lambda_n / mu,
 //           SVT_tau(P_n) = W diag((s_i - tau)_+ / s_i) W^T P_n (eq. (13)); the
@@ -443,18 +445,31 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
 // (k, c) = (lane % 16, lane / 16) adds rows 16c..16c+15 of column k from LDS;
 // two xor-shuffles combine the four quarters.  The order is fixed.
 constexpr int kBatchLds = 64 * 17 + 32;
-template <int K>
+// kBlock: the wave is the whole block (__syncthreads); otherwise it is one
+// wave of a larger block working alone on its own LDS region, where the LDS
+// accesses of a wave take effect in program order and only the compiler has
+// to be kept from reordering them.
+template <bool kBlock>
+__device__ __forceinline__ void qr_sync() {
+  if constexpr (kBlock) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+template <int K, bool kBlock = true>
 __device__ __forceinline__ void wave_sum_bcast(double (&v)[K], double (&row)[K], int src,
                                                double* lds) {
   constexpr int LD = K + 1;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < K; ++k) lds[lane * LD + k] = v[k];
   if (lane == src) {
 #pragma unroll
     for (int k = 0; k < K; ++k) lds[64 * 17 + 16 + k] = row[k];
   }
-  __syncthreads();
+  qr_sync<kBlock>();
   const int k = lane & 15, c = lane >> 4;
   double s = 0;
   if (k < K) {
@@ -464,20 +479,20 @@ __device__ __forceinline__ void wave_sum_bcast(double (&v)[K], double (&row)[K],
   s += __shfl_xor(s, 16, 64);
   s += __shfl_xor(s, 32, 64);
   if (lane < K) lds[64 * 17 + lane] = s;
-  __syncthreads();
+  qr_sync<kBlock>();
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     v[kk] = lds[64 * 17 + kk];
     row[kk] = lds[64 * 17 + 16 + kk];
   }
-  __syncthreads();
+  qr_sync<kBlock>();
 }
 
 // One Householder step on column C (compile-time, so every register index is
 // static): with d_j = sum_{i > C} a_iC a_ij for j >= C (d_C is the squared norm
 // below the diagonal), the reflector v = (1, a_{i>C,C} / (alpha - beta)) gives
 // w_j = v^T a_j = a_Cj + d_j / (alpha - beta); one batched reduction per column.
-template <int C, int TR, int RP>
+template <int C, int TR, int RP, bool kBlock = true>
 __device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)[RP], int R,
                                               int lane, double* lds) {
   if constexpr (C < RP) {
@@ -493,7 +508,7 @@ __device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)
         d[jj] = s;
         row[jj] = a[0][C + jj];  // row C lives in lane C, slot 0
       }
-      wave_sum_bcast<K>(d, row, C, lds);
+      wave_sum_bcast<K, kBlock>(d, row, C, lds);
       const double xnorm2 = d[0];
       const double alpha = row[0];
       double tc = 0, beta = alpha, scale = 0;
@@ -516,13 +531,13 @@ __device__ __forceinline__ void qr_factor_col(double (&a)[TR][RP], double (&tau)
       }
       tau[C] = tc;
     }
-    qr_factor_col<C + 1, TR, RP>(a, tau, R, lane, lds);
+    qr_factor_col<C + 1, TR, RP, kBlock>(a, tau, R, lane, lds);
   }
 }
 
 // Backward accumulation of Q = H_0 ... H_{R-1} [I_R; 0], column C down to 0:
 // w_j = a_Cj + sum_{i > C} v_i a_ij for j > C, then column C becomes H_C e_C.
-template <int C, int TR, int RP>
+template <int C, int TR, int RP, bool kBlock = true>
 __device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&tau)[RP], int R,
                                             int lane, double* lds) {
   if constexpr (C >= 0) {
@@ -540,7 +555,7 @@ __device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&
           d[jj] = s;
           row[jj] = a[0][C + 1 + jj];
         }
-        wave_sum_bcast<K>(d, row, C, lds);
+        wave_sum_bcast<K, kBlock>(d, row, C, lds);
 #pragma unroll
         for (int t = 0; t < TR; ++t) {
           const int i = lane + 64 * t;
@@ -555,7 +570,7 @@ __device__ __forceinline__ void qr_form_col(double (&a)[TR][RP], const double (&
         a[t][C] = i > C ? -tc * a[t][C] : (i == C ? 1.0 - tc : 0.0);
       }
     }
-    qr_form_col<C - 1, TR, RP>(a, tau, R, lane, lds);
+    qr_form_col<C - 1, TR, RP, kBlock>(a, tau, R, lane, lds);
   }
 }
 
@@ -612,6 +627,222 @@ __global__ void __launch_bounds__(64) k_qr_reg(Batch<S> bt) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cholesky QR on the FP64 matrix cores, for I <= 256 and R <= 12: four waves,
+// wave w owns rows 64w .. 64w + 63 of the I x R matrix A (first A = M_n).
+// One pass:
+//   C = A^T A   v_mfma_f64_16x16x4 with both operands the wave's rows (lane
+//               (p, q) supplies A[64w + 4s + q][p], four rows per step); the
+//               four 16 x 16 partials are summed in LDS in a fixed order;
+//   X = R^-1    for C = R^T R, factored and inverted in registers by every
+//               lane of every wave (the same arithmetic everywhere, so no lane
+//               waits for another);
+//   A <- A X    v_mfma_f64_16x16x4, row block b (16 rows) of the wave times X.
+// Two passes are CholeskyQR2 (Yamamoto, Nakatsukasa, Yanagisawa and Fukaya,
+// ETNA 44, 2015): with A well conditioned the result is orthonormal to
+// rounding; range(A X) = range(A) and R has a positive diagonal, so it is the
+// Householder Q up to the signs of its columns.  A pass fails when a pivot
+// (the squared norm of column j outside the span of the columns before it) is
+// below floor2 times the squared norm of column j: 1e-12 in the first pass
+// (column j within 1e-6 of that span), 1/2 in the second (the first result
+// far from orthonormal).  Then wave 0 computes the Householder QR of M_n
+// instead, which stays orthonormal when M_n is rank deficient, and the other
+// waves leave.  Columns j >= R are zero and get r_jj = 1.
+// ---------------------------------------------------------------------------
+template <int RP>
+struct Tri {
+  static constexpr int n = RP * (RP + 1) / 2;
+  // (j, k), j <= k, in the packed upper triangle stored row by row
+  static __device__ __forceinline__ constexpr int at(int j, int k) {
+    return j * RP - j * (j - 1) / 2 + (k - j);
+  }
+};
+
+// c: the upper triangle of C in, of X = R^-1 out (C = R^T R).  Row j of R is
+// r_jl = (c_jl - sum_{k<j} r_kj r_kl) / r_jj; column j of X is x_jj = 1/r_jj,
+// x_ij = -x_jj sum_{i<=k<j} x_ik r_kj (columns < j of X are final by then).
+template <int RP>
+__device__ __forceinline__ bool chol_inv(double (&c)[Tri<RP>::n], int R, double floor2) {
+  bool good = true;
+  double h[RP];
+#pragma unroll
+  for (int j = 0; j < RP; ++j) {
+    const double cjj = c[Tri<RP>::at(j, j)];
+    double d = cjj;
+#pragma unroll
+    for (int k = 0; k < j; ++k) d = fma(-c[Tri<RP>::at(k, j)], c[Tri<RP>::at(k, j)], d);
+    const bool real = j < R;
+    good = good && (!real || d > floor2 * cjj);
+    const double hj = (real && d > 0.0) ? rsqrt_nr(d) : 1.0;
+    h[j] = hj;
+#pragma unroll
+    for (int l = j + 1; l < RP; ++l) {
+      double t = c[Tri<RP>::at(j, l)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t = fma(-c[Tri<RP>::at(k, j)], c[Tri<RP>::at(k, l)], t);
+      c[Tri<RP>::at(j, l)] = real ? t * hj : 0.0;
+    }
+    c[Tri<RP>::at(j, j)] = real ? d * hj : 1.0;
+  }
+#pragma unroll
+  for (int j = 0; j < RP; ++j) {
+    double tmp[RP];
+#pragma unroll
+    for (int i = 0; i < j; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = i; k < j; ++k) t = fma(c[Tri<RP>::at(i, k)], c[Tri<RP>::at(k, j)], t);
+      tmp[i] = -h[j] * t;
+    }
+#pragma unroll
+    for (int i = 0; i < j; ++i) c[Tri<RP>::at(i, j)] = tmp[i];
+    c[Tri<RP>::at(j, j)] = h[j];
+  }
+  return good;
+}
+
+template <typename S, int RP>
+__global__ void __launch_bounds__(256) k_qr_chol(Batch<S> bt) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int NG = Tri<RP>::n;
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int n = blockIdx.x - bt.start[req];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int I = g.I, R = g.R, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  __shared__ double Cp[4][kRT * kRT];       // per-wave Gram partials
+  __shared__ double Cs[kRT * kRT];          // the Gram
+  __shared__ double Xw[4][kRT][kRT + 1];    // X, one copy per wave (zero below the diagonal)
+  __shared__ double Tw[4][64][kRT + 1];     // a wave's rows, for the change of operand layout
+  __shared__ double hl[kBatchLds];          // Householder QR of wave 0
+  for (int e = tid; e < 4 * kRT * (kRT + 1); e += 256) (&Xw[0][0][0])[e] = 0.0;
+  const double* M = mb.M;
+  // every load first (rows clamped into range), then the masks; the wave's
+  // 64 x 16 tile also goes to LDS, from where the other operand layout is read
+  // (so that it is not held in registers through the factorisation)
+  double gA[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int i = 64 * w + 4 * s + q;
+    gA[s] = *(const __attribute__((address_space(1))) double*)(M + (int64_t)(i < I ? i : I - 1) * kRT + p);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int i = 64 * w + 4 * s + q;
+    gA[s] = (i < I && p < R) ? gA[s] : 0.0;
+    Tw[w][4 * s + q][p] = gA[s];
+  }
+  d4 out[4];
+  bool ok = true;
+  // not unrolled: one copy of the pass in the instruction stream (these
+  // kernels run once per iteration, with a cold instruction cache)
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(gA[s], gA[s], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Cp[w][(4 * v + q) * kRT + p] = acc[v];
+    __syncthreads();
+    Cs[tid] = ((Cp[0][tid] + Cp[1][tid]) + Cp[2][tid]) + Cp[3][tid];
+    __syncthreads();
+    double c[NG];
+#pragma unroll
+    for (int j = 0; j < RP; ++j)
+#pragma unroll
+      for (int k = j; k < RP; ++k) c[Tri<RP>::at(j, k)] = Cs[j * kRT + k];
+    ok = chol_inv<RP>(c, R, pass == 0 ? 1e-12 : 0.5);
+    ok = __builtin_amdgcn_readfirstlane(ok ? 1 : 0) != 0;
+    if (!ok) break;
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < RP; ++j)
+#pragma unroll
+        for (int k = j; k < RP; ++k) Xw[w][j][k] = c[Tri<RP>::at(j, k)];
+    }
+    qr_sync<false>();
+    double xb[4], aA[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) xb[s] = Xw[w][4 * s + q][p];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) aA[b][s] = Tw[w][16 * b + p][4 * s + q];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      d4 o = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) o = __builtin_amdgcn_mfma_f64_16x16x4f64(aA[b][s], xb[s], o, 0, 0, 0);
+      out[b] = o;
+    }
+    if (pass == 0) {
+      // out[b][v] = A[64w + 16b + 4v + q][p]: the Gram layout of the next pass
+      // as it stands (s = 4b + v), and the tile for the other layout
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          gA[4 * b + v] = out[b][v];
+          Tw[w][16 * b + 4 * v + q][p] = out[b][v];
+        }
+      qr_sync<false>();
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 64 * w + 16 * b + 4 * v + q;
+        if (i < I) {
+          if (p < R) mb.U[(int64_t)i * R + p] = out[b][v];
+          mb.Us[(int64_t)i * kRT + p] = (S)(p < R ? out[b][v] : 0.0);
+        }
+      }
+    return;
+  }
+  if (w != 0) return;
+  // Householder QR of M_n by wave 0 alone (its own LDS region, no block barrier)
+  constexpr int TR = 4;
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  double a[TR][RP];
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int i = lane + 64 * t;
+    const double* row = M + (int64_t)(i < I ? i : I - 1) * kRT;
+#pragma unroll
+    for (int c = 0; c < RP; c += 2) {
+      const d2v v = *reinterpret_cast<const d2v*>(row + c);
+      a[t][c] = (i < I && c < R) ? v[0] : 0.0;
+      a[t][c + 1] = (i < I && c + 1 < R) ? v[1] : 0.0;
+    }
+  }
+  double tau[RP];
+#pragma unroll
+  for (int c = 0; c < RP; ++c) tau[c] = 0.0;
+  qr_factor_col<0, TR, RP, false>(a, tau, R, lane, hl);
+  qr_form_col<RP - 1, TR, RP, false>(a, tau, R, lane, hl);
+#pragma unroll
+  for (int t = 0; t < TR; ++t) {
+    const int i = lane + 64 * t;
+    if (i < I) {
+#pragma unroll
+      for (int c = 0; c < RP; ++c)
+        if (c < R) mb.U[(int64_t)i * R + c] = a[t][c];
+#pragma unroll
+      for (int c = 0; c < kRT; ++c) {
+        double v = 0.0;
+        if (c < RP) v = c < R ? a[t][c < RP ? c : 0] : 0.0;
+        mb.Us[(int64_t)i * kRT + c] = (S)v;
+      }
+    }
+  }
+}
+
 template <typename S, int TR>
 static bool qr_reg_rp(const Batch<S>& b, int grid, int rmax, hipStream_t s) {
   if (rmax <= 4) {
@@ -642,6 +873,17 @@ void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
       rmax = ls.host[r]->g[n].R > rmax ? ls.host[r]->g[n].R : rmax;
     }
   bool done = false;
+  if (imax <= 256 && rmax <= 12) {
+    // the factorisation is unrolled to R rounded up to even
+    switch ((rmax + 1) / 2) {
+      case 1:
+      case 2: hipLaunchKernelGGL((k_qr_chol<S, 4>), dim3(grid), dim3(256), 0, s, b); return;
+      case 3: hipLaunchKernelGGL((k_qr_chol<S, 6>), dim3(grid), dim3(256), 0, s, b); return;
+      case 4: hipLaunchKernelGGL((k_qr_chol<S, 8>), dim3(grid), dim3(256), 0, s, b); return;
+      case 5: hipLaunchKernelGGL((k_qr_chol<S, 10>), dim3(grid), dim3(256), 0, s, b); return;
+      default: hipLaunchKernelGGL((k_qr_chol<S, 12>), dim3(grid), dim3(256), 0, s, b); return;
+    }
+  }
   if (imax <= 64)
     done = qr_reg_rp<S, 1>(b, grid, rmax, s);
   else if (imax <= 128)
