@@ -636,6 +636,7 @@ int gemm_m_blocks(const ModeGeom& g, int N) {
 }
 
 int gram_blocks(const ModeGeom& g) {
+  // at most 64: the eigensolver loads every partial in one pass
   const int64_t steps = (g.J + 15) / 16;
   int64_t want = 64;
   int64_t maxb = (steps + 3) / 4;

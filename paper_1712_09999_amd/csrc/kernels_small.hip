@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(64) k_qr(Batch<S> bt) {
 // (and |s_pq| > 1e-150, see jacobi_needed).
 // W_f is a spectral function of S, so it does not depend on W0 beyond rounding.
 // ---------------------------------------------------------------------------
-constexpr int kEigParts = 32;  // Gram partials summed in one pass of loads
+constexpr int kEigParts = 64;  // Gram partials (at most; see gram_blocks), loaded in one pass
 
 // Pair idx of round rd of the round-robin (chess tournament) ordering of the
 // indices 0 .. m (m odd): index m stays, the others rotate; p < q.
@@ -255,27 +255,24 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
       const int e = tid + 256 * u;
       uv[u] = mb.U[e < nU ? e : nU - 1];
     }
+    const double wev = mb.Wev[tid];
+    // every partial in one pass of loads (the Gram kernel writes at most
+    // kEigParts of them), static register indices (no private memory)
     const int nb = mb.sblocks;
     const double* sp = mb.Spart + tid;
     double part[kEigParts];
 #pragma unroll
-    for (int b = 0; b < kEigParts; ++b) part[b] = 0.0;
-    // kEigParts partials per pass, static register indices (no private memory)
-    for (int b0 = 0; b0 < nb; b0 += kEigParts) {
-      double v[kEigParts];
+    for (int b = 0; b < kEigParts; ++b) part[b] = sp[(int64_t)(b < nb ? b : nb - 1) * kRT * kRT];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int b = 0; b < kEigParts; ++b) v[b] = sp[(int64_t)(b0 + b < nb ? b0 + b : nb - 1) * kRT * kRT];
-#pragma unroll
-      for (int b = 0; b < kEigParts; ++b)
-        if (in && b0 + b < nb) part[b] += v[b];
-    }
+    for (int b = 0; b < kEigParts; ++b) part[b] = (in && b < nb) ? part[b] : 0.0;
     // fixed-order pairwise sum of the partials
 #pragma unroll
     for (int w = kEigParts / 2; w > 0; w /= 2)
 #pragma unroll
       for (int b = 0; b < w; ++b) part[b] += part[b + w];
     Sm[r][c] = part[0];
-    W[r][c] = (warm && in) ? mb.Wev[tid] : (r == c ? 1.0 : 0.0);
+    W[r][c] = (warm && in) ? wev : (r == c ? 1.0 : 0.0);
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int e = tid + 256 * u;
