@@ -631,9 +631,10 @@ __global__ void __launch_bounds__(64) k_qr_reg(Batch<S> bt) {
 //   C = A^T A   v_mfma_f64_16x16x4 with both operands the wave's rows (lane
 //               (p, q) supplies A[64w + 4s + q][p], four rows per step); the
 //               four 16 x 16 partials are summed in LDS in a fixed order;
-//   X = R^-1    for C = R^T R, factored and inverted in registers by every
-//               lane of every wave (the same arithmetic everywhere, so no lane
-//               waits for another);
+//   X = R^-1    for C = R^T R, factored in registers by every lane of every
+//               wave (the same arithmetic everywhere, so no lane waits for
+//               another); each lane then solves for the column of X it
+//               supplies to the next product;
 //   A <- A X    v_mfma_f64_16x16x4, row block b (16 rows) of the wave times X.
 // Two passes are CholeskyQR2 (Yamamoto, Nakatsukasa, Yanagisawa and Fukaya,
 // ETNA 44, 2015): with A well conditioned the result is orthonormal to
@@ -655,13 +656,12 @@ struct Tri {
   }
 };
 
-// c: the upper triangle of C in, of X = R^-1 out (C = R^T R).  Row j of R is
-// r_jl = (c_jl - sum_{k<j} r_kj r_kl) / r_jj; column j of X is x_jj = 1/r_jj,
-// x_ij = -x_jj sum_{i<=k<j} x_ik r_kj (columns < j of X are final by then).
+// c: the upper triangle of C in, of R out (C = R^T R), h[j] = 1 / r_jj.  Row j
+// of R is r_jl = (c_jl - sum_{k<j} r_kj r_kl) / r_jj.
 template <int RP>
-__device__ __forceinline__ bool chol_inv(double (&c)[Tri<RP>::n], int R, double floor2) {
+__device__ __forceinline__ bool chol_fact(double (&c)[Tri<RP>::n], double (&h)[RP], int R,
+                                          double floor2) {
   bool good = true;
-  double h[RP];
 #pragma unroll
   for (int j = 0; j < RP; ++j) {
     const double cjj = c[Tri<RP>::at(j, j)];
@@ -681,21 +681,22 @@ __device__ __forceinline__ bool chol_inv(double (&c)[Tri<RP>::n], int R, double 
     }
     c[Tri<RP>::at(j, j)] = real ? d * hj : 1.0;
   }
-#pragma unroll
-  for (int j = 0; j < RP; ++j) {
-    double tmp[RP];
-#pragma unroll
-    for (int i = 0; i < j; ++i) {
-      double t = 0.0;
-#pragma unroll
-      for (int k = i; k < j; ++k) t = fma(c[Tri<RP>::at(i, k)], c[Tri<RP>::at(k, j)], t);
-      tmp[i] = -h[j] * t;
-    }
-#pragma unroll
-    for (int i = 0; i < j; ++i) c[Tri<RP>::at(i, j)] = tmp[i];
-    c[Tri<RP>::at(j, j)] = h[j];
-  }
   return good;
+}
+
+// Column col of X = R^-1 by back substitution, R x = e_col:
+// x_i = (delta_i,col - sum_{k>i} r_ik x_k) / r_ii (zero below col; zero
+// altogether for col >= RP).
+template <int RP>
+__device__ __forceinline__ void tri_inv_col(const double (&c)[Tri<RP>::n], const double (&h)[RP],
+                                            int col, double (&x)[RP]) {
+#pragma unroll
+  for (int i = RP - 1; i >= 0; --i) {
+    double t = i == col ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = i + 1; k < RP; ++k) t = fma(-c[Tri<RP>::at(i, k)], x[k], t);
+    x[i] = t * h[i];
+  }
 }
 
 template <typename S, int RP>
@@ -712,10 +713,8 @@ __global__ void __launch_bounds__(256) k_qr_chol(Batch<S> bt) {
   const int p = lane & 15, q = lane >> 4;
   __shared__ double Cp[4][kRT * kRT];       // per-wave Gram partials
   __shared__ double Cs[kRT * kRT];          // the Gram
-  __shared__ double Xw[4][kRT][kRT + 1];    // X, one copy per wave (zero below the diagonal)
   __shared__ double Tw[4][64][kRT + 1];     // a wave's rows, for the change of operand layout
   __shared__ double hl[kBatchLds];          // Householder QR of wave 0
-  for (int e = tid; e < 4 * kRT * (kRT + 1); e += 256) (&Xw[0][0][0])[e] = 0.0;
   const double* M = mb.M;
   // every load first (rows clamped into range), then the masks; the wave's
   // 64 x 16 tile also goes to LDS, from where the other operand layout is read
@@ -752,19 +751,22 @@ __global__ void __launch_bounds__(256) k_qr_chol(Batch<S> bt) {
     for (int j = 0; j < RP; ++j)
 #pragma unroll
       for (int k = j; k < RP; ++k) c[Tri<RP>::at(j, k)] = Cs[j * kRT + k];
-    ok = chol_inv<RP>(c, R, pass == 0 ? 1e-12 : 0.5);
+    double h[RP];
+    ok = chol_fact<RP>(c, h, R, pass == 0 ? 1e-12 : 0.5);
     ok = __builtin_amdgcn_readfirstlane(ok ? 1 : 0) != 0;
     if (!ok) break;
-    if (lane == 0) {
-#pragma unroll
-      for (int j = 0; j < RP; ++j)
-#pragma unroll
-        for (int k = j; k < RP; ++k) Xw[w][j][k] = c[Tri<RP>::at(j, k)];
-    }
-    qr_sync<false>();
+    // lane (p, q) needs X[4s + q][p]: column p of X, solved in the lane
+    double x[RP];
+    tri_inv_col<RP>(c, h, p, x);
     double xb[4], aA[4][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) xb[s] = Xw[w][4 * s + q][p];
+    for (int s = 0; s < 4; ++s) {
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (4 * s + j < RP) v = q == j ? x[4 * s + j < RP ? 4 * s + j : 0] : v;
+      xb[s] = v;
+    }
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
