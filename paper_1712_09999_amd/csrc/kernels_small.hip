@@ -149,9 +149,15 @@ __global__ void __launch_bounds__(64) k_qr(Batch<S> bt) {
 //     issues all of its reads first, reads the matrix from one buffer and
 //     writes the other, so a round has one barrier;
 //  5. W_f = W diag(f) W^T and U W_f (FP64 MFMA).
-// A pair is rotated while |s_pq| > thr sqrt(|s_pp s_qq|), thr = 4e-16 for an
-// FP64 state and 1e-10 for FP32, whose factors U W_f are rounded to 2^-24
-// (and |s_pq| > 1e-150, see jacobi_needed).
+// A pair is rotated while |s_pq| > thr sqrt(|s_pp s_qq|) (and |s_pq| > 1e-150,
+// see jacobi_needed), thr = 4e-16 for an FP64 state and 2^-24 for FP32.  Why
+// that suffices: W_f = F(S) with F(l) = (1 - tau / sqrt(l))_+ on the
+// eigenvalues, and a remaining off-diagonal entry e of the rotated S moves
+// W_f by about |e| times the divided difference (F(l_p) - F(l_q)) / (l_p - l_q),
+// which is at most 1 / (2 sqrt(l_p l_q)) (with x = sqrt(l_p) > y = sqrt(l_q)
+// >= tau it equals tau / (x y (x + y)); below tau^2 F is zero); so with
+// |e| <= thr sqrt(l_p l_q) W_f moves by at most thr / 2, under the rounding of
+// the FP32 factors U W_f.
 // W_f is a spectral function of S, so it does not depend on W0 beyond rounding.
 // ---------------------------------------------------------------------------
 constexpr int kEigParts = 64;  // Gram partials (at most; see gram_blocks), loaded in one pass
@@ -297,7 +303,7 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
     Sm[r][c] = (r < R && c < R) ? v : 0.0;
   }
   __syncthreads();
-  const double thr = sizeof(S) == 4 ? 1.0e-10 : 4.0e-16;
+  const double thr = sizeof(S) == 4 ? 5.9604644775390625e-08 : 4.0e-16;
   const int Rp = R + (R & 1);
   const int half = Rp / 2;
   const int m = Rp - 1;
