@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = lane & 15, q = lane >> 4;
   __shared__ double red[kMWaves][64][4];
-  double* __restrict__ out = mb.Mpart + (int64_t)blk * g.I * kRT;
+  double* __restrict__ out = mb.Mpart + (int64_t)blk * g.I * g.R;  // [I][R] partial
 
   if (g.B > 1) {
     constexpr int IBP = sizeof(S) == 4 ? 8 : 4;  // row blocks per pass (register budget)
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
 #pragma unroll
           for (int w = 0; w < kMWaves; ++w) s += red[w][l][v];
           const int i = (ib0 + u) * 16 + MM<S>::row(l >> 4, v);
-          if (i < g.I) out[(int64_t)i * kRT + (l & 15)] = s;
+          if (i < g.I && (l & 15) < g.R) out[(int64_t)i * g.R + (l & 15)] = s;
         }
         __syncthreads();
       }
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
             // D[m = row(l>>4, v)][n = l&15] -> i = 64(c0+c) + 4m + t
             const int m = MM<S>::row(l >> 4, v);
             const int i = (c0 + c) * 64 + 4 * m + t;
-            if (i < g.I) out[(int64_t)i * kRT + (l & 15)] = s;
+            if (i < g.I && (l & 15) < g.R) out[(int64_t)i * g.R + (l & 15)] = s;
           }
           __syncthreads();
         }
@@ -498,7 +498,8 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   }
 }
 
-// Fixed-order reduction of the GEMM-M partials: M[i][r] = sum_blk Mpart[blk][i][r].
+// Fixed-order reduction of the GEMM-M partials: M[i][r] = sum_blk Mpart[blk][i][r]
+// (partials I x R, the reduced M in rows of kRT whose columns >= R are unused).
 // A block owns 64 consecutive entries; its 4 thread groups sum interleaved
 // partials with independent loads in flight, then combine in a fixed order.
 template <typename S>
@@ -512,7 +513,7 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   const ModeBufs<S> mb = pb.m[n];
   const int grp = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)(lb - pb.kb[KB_REDUCE_M][n]) * 64 + l;
-  const int64_t ne = (int64_t)g.I * kRT;
+  const int64_t ne = (int64_t)g.I * g.R;
   __shared__ double part[4][64];
   double acc[4] = {0, 0, 0, 0};
   if (e < ne) {
@@ -536,7 +537,10 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   }
   part[grp][l] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
-  if (grp == 0 && e < ne) mb.M[e] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+  if (grp == 0 && e < ne) {
+    const int64_t i = e / g.R;
+    mb.M[i * kRT + (e - i * g.R)] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -647,7 +651,7 @@ int gemm_p_blocks(const ModeGeom& g) {
   return (int)(g.B > 1 ? (g.J + 63) / 64 : (g.A + 63) / 64);
 }
 
-int reduce_m_blocks(const ModeGeom& g) { return (int)(((int64_t)g.I * kRT + 63) / 64); }
+int reduce_m_blocks(const ModeGeom& g) { return (int)(((int64_t)g.I * g.R + 63) / 64); }
 
 template <typename S>
 static int mode_grid(const Problem<S>& p, int kind) { return p.kb[kind][p.N]; }

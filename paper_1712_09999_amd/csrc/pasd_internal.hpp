@@ -67,8 +67,8 @@ struct ModeBufs {
   S* Us;         // I x kRT  U in the state type, zero-padded columns (GEMM-P operand)
   S* Uf;         // I x kRT  U W (SVT-folded factor), padded rows of 16
   S* UfT;        // kRT x I  transposed copy (last mode uses it)
-  double* Mpart; // GEMM-M split-K partials [nblk][I][kRT] (double)
-  double* M;     // reduced M, I x kRT
+  double* Mpart; // GEMM-M split-K partials [nblk][I][R] (double)
+  double* M;     // reduced M, I x kRT (columns >= R unused)
   double* Spart; // Gram partials [nblk][kRT][kRT]
   double* Wf;    // kRT x kRT SVT factor
   double* Wev;   // kRT x kRT eigenvectors of the last Gram (warm start)
