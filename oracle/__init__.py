@@ -14,6 +14,7 @@ from .pasd_oracle import (  # noqa: F401
     pasd_output,
     pasd_solve,
     polar,
+    procrustes_keep,
     prox_l1,
     svt,
     unfold,

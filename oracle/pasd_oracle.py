@@ -27,6 +27,17 @@ Readings of points the paper leaves open (each is argued in the design notes):
   only), and one of its minimisers otherwise.  Using P instead of V also keeps
   the step well conditioned when a singular value has just crossed the
   threshold.
+  The alternative tie-break ``tiebreak="keep"`` (reading R1') solves eq. (10)
+  with ``G_n^k (V_n^k)^T`` itself and, on the directions where V_n^k vanishes,
+  keeps U_n^k: among the maximisers of <U, A> over column-orthonormal U
+  (A = G_n^k (V_n^k)^T of rank r, thin SVD A = Ua S Va^T) it takes
+  ``Ua_r Va_r^T + C B^T`` with B the last R_n - r columns of Va (the null
+  space of A) and C the polar factor of (I - Ua_r Ua_r^T) U_n^k B, the
+  orthonormal completion nearest U_n^k (the limit of polar(A + eps U_n^k) as
+  eps -> 0+).  At k = 0 (V = 0) this gives U^1 = U^0, as does the default.
+  Parity status of this variant: pinned by the same tests (it equals the
+  default wherever V_n^k has full rank) and by a brute-force search over the
+  completion on small cases.
 * The weights ``lambda_n`` default to sqrt(max(I_n, J_n)) / N (Section 5.1).
 * The output weights ``alpha_n`` of Algorithm 1 are undefined in the paper;
   the oracle takes ``alpha_n = lambda_n``.
@@ -95,6 +106,22 @@ def polar(M: np.ndarray) -> np.ndarray:
     return U @ Vt
 
 
+def procrustes_keep(A: np.ndarray, r: int, U_prev: np.ndarray) -> np.ndarray:
+    """Eq. (10) for A = G V^T of rank r with the completion nearest U_prev on
+    the null space of A (reading R1'): Ua_r Va_r^T + C B^T, where A = Ua S Va^T,
+    B = Va[:, r:] and C = polar((I - Ua_r Ua_r^T) U_prev B)."""
+    R = A.shape[1]
+    Ua, _, Vat = np.linalg.svd(A, full_matrices=False)
+    Va = Vat.T
+    U = Ua[:, :r] @ Va[:, :r].T
+    if r < R:
+        B = Va[:, r:]
+        X = U_prev @ B
+        X = X - Ua[:, :r] @ (Ua[:, :r].T @ X)
+        U = U + polar(X) @ B.T
+    return U
+
+
 def default_lambdas(dims: Sequence[int]) -> List[float]:
     """lambda_n = sqrt(max(I_n, prod_{m != n} I_m)) / N (Section 5.1)."""
     N = len(dims)
@@ -127,6 +154,8 @@ class OracleState:
     history: List[List[float]] = dataclasses.field(default_factory=list)
     # Quantities of the last completed iteration, kept for the invariant tests.
     last: dict = dataclasses.field(default_factory=dict)
+    # Procrustes tie-break: "pre" (default, G P^T) or "keep" (reading R1')
+    tiebreak: str = "pre"
 
     @property
     def N(self) -> int:
@@ -135,7 +164,7 @@ class OracleState:
 
 def pasd_init(T: np.ndarray, ranks: Sequence[int], lam: Optional[Sequence[float]] = None,
               alpha: Optional[Sequence[float]] = None, mu0: float = 1e-4,
-              mu_max: float = 1e10, rho: float = 1.1) -> OracleState:
+              mu_max: float = 1e10, rho: float = 1.1, tiebreak: str = "pre") -> OracleState:
     """Initialisation of Algorithm 1: U_n^0 = eye(I_n, R_n), V_n^0 = 0,
     Y_n^0 = 0, E^0 = 0, mu^0 = 1e-4, mu_max = 1e10, rho = 1.1."""
     T = np.asarray(T, dtype=np.float64)
@@ -150,7 +179,7 @@ def pasd_init(T: np.ndarray, ranks: Sequence[int], lam: Optional[Sequence[float]
     return OracleState(
         T=T, ranks=ranks, lam=lam, alpha=alpha, mu=float(mu0), mu_max=float(mu_max),
         rho=float(rho), k=0, U=U, V=V, P=[None] * N, Z=[np.zeros_like(T) for _ in range(N)],
-        E=np.zeros_like(T), Y=[np.zeros_like(T) for _ in range(N)])
+        E=np.zeros_like(T), Y=[np.zeros_like(T) for _ in range(N)], tiebreak=str(tiebreak))
 
 
 def pasd_iterate(st: OracleState, count: int = 1, tol: Optional[float] = None) -> OracleState:
@@ -172,6 +201,8 @@ def pasd_iterate(st: OracleState, count: int = 1, tol: Optional[float] = None) -
         for n in range(N):
             if st.k == 0:
                 U_new.append(st.U[n].copy())
+            elif st.tiebreak == "keep":
+                U_new.append(procrustes_keep(G[n] @ st.V[n].T, st.rank[n], st.U[n]))
             else:
                 U_new.append(polar(G[n] @ st.P[n].T))
         # V-step, eq. (13): V_n = SVT_{lambda_n / mu^k}(U_n^T G_n^k).
@@ -213,9 +244,9 @@ def pasd_output(st: OracleState):
 
 def pasd_solve(T: np.ndarray, ranks: Sequence[int], lam=None, alpha=None, tol: float = 1e-5,
                max_iter: int = 1000, mu0: float = 1e-4, mu_max: float = 1e10,
-               rho: float = 1.1):
+               rho: float = 1.1, tiebreak: str = "pre"):
     """Algorithm 1 to convergence or ``max_iter``; returns (X, E, state)."""
-    st = pasd_init(T, ranks, lam, alpha, mu0, mu_max, rho)
+    st = pasd_init(T, ranks, lam, alpha, mu0, mu_max, rho, tiebreak)
     while st.k < max_iter:
         pasd_iterate(st, 1)
         if max(st.residual) < tol:
