@@ -87,8 +87,14 @@ typedef struct {
 } pasd_config;
 
 enum pasd_flags {
-  PASD_FLAG_NO_GRAPH = 1  /* launch every kernel directly instead of replaying a captured
-                             HIP graph of 16 iterations (same results, bitwise) */
+  PASD_FLAG_NO_GRAPH = 1,     /* launch every kernel directly instead of replaying a captured
+                                 HIP graph of 16 iterations (same results, bitwise) */
+  PASD_FLAG_TIEBREAK_KEEP = 2 /* Procrustes tie-break of eq. (10) when V_n^k is rank deficient:
+                                 span U_n^{k+1} = range(G_n^k (V_n^k)^T) plus, on the directions
+                                 where V_n^k vanishes, the previous U_n^k (the maximiser of
+                                 eq. (10) nearest U_n^k).  Default (flag clear): span U_n^{k+1}
+                                 = range(G_n^k (P_n^k)^T) with the pre-threshold P_n^k.  Both
+                                 agree while every V_n^k has full rank; at k = 0 both keep U^0 */
 };
 
 /* Progress and status of a context. */
@@ -124,8 +130,11 @@ enum pasd_quantity {
   PASD_Q_SCALARS = 7, /* double[2] = {k, mu} */
   PASD_Q_D = 8,       /* D = T - E as the solver stores it (numel, state dtype); a
                          checkpoint of D (not E) restores the iterate bitwise */
-  PASD_Q_WEV = 9      /* eigenvectors of the last Gram P_n P_n^T, the starting basis
+  PASD_Q_WEV = 9,     /* eigenvectors of the last Gram P_n P_n^T, the starting basis
                          of the next eigensolve: R_n x R_n row-major, double */
+  PASD_Q_FAC = 10     /* SVT weights f_i = (s_i - tau)_+ / s_i of the last eigensolve, in the
+                         order of the columns of PASD_Q_WEV: R_n doubles (the keep tie-break
+                         of PASD_FLAG_TIEBREAK_KEEP reads them at the next iteration) */
 };
 
 /* Fill cfg with defaults (order 0, no dims).  Host only. */
@@ -187,7 +196,8 @@ int pasd_step_batch(pasd_ctx *const *ctxs, int count, int n_iters);
 enum pasd_kernel {
   PASD_K_GEMM_M = 0,  /* M_n = G_n P_n^T split-K partials (eq. (10) operand) */
   PASD_K_REDUCE_M,    /* fixed-order reduction of the partials */
-  PASD_K_QR,          /* U_n = Householder Q of M_n */
+  PASD_K_QR,          /* U_n = orthonormal basis of range(M_n) (CholeskyQR2 or Householder;
+                         with PASD_FLAG_TIEBREAK_KEEP the tie-break transform of M_n first) */
   PASD_K_GEMM_P,      /* P_n = U_n^T G_n (eq. (13) operand) */
   PASD_K_GRAM,        /* S_n = P_n P_n^T partials */
   PASD_K_EIG,         /* Jacobi eigensolver of S_n, SVT factor */

@@ -386,6 +386,7 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
       f = sig > tau ? (sig - tau) / sig : 0.0;
     }
     fac[tid] = f;
+    mb.Fac[tid] = f;
   }
   __syncthreads();
   if (tid < 64) {
@@ -865,12 +866,64 @@ static bool qr_reg_rp(const Batch<S>& b, int grid, int rmax, hipStream_t s) {
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Tie-break of eq. (10) that keeps U_n^k on the directions where V_n^k
+// vanishes (PASD_FLAG_TIEBREAK_KEEP).  With S = P P^T = W diag(l) W^T from the
+// previous eigensolve and f_i its SVT weights, V^k = W diag(f) W^T P^k, so
+// G V^T = M W diag(f) W^T with M = G P^T the reduced GEMM-M result; its range
+// is spanned by the columns (M W)_i with f_i > 0, and the maximiser of eq. (10)
+// nearest U^k completes it on span{(U^k W)_i : f_i = 0}.  Any basis of that
+// span serves (the iterates depend on range(U) only), so M is replaced in
+// place by the R columns (M W)_i (f_i > 0) and (U^k W)_i (f_i = 0), and the QR
+// that follows orthonormalises them.  One block per (problem, mode); a thread
+// per row.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_tiebreak(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (!pb.tiebreak_keep || pb.sc->done || pb.sc->k == 0) return;
+  const int n = blockIdx.x - bt.start[req];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int I = g.I, R = g.R, tid = threadIdx.x;
+  __shared__ double W[kRT][kRT];
+  __shared__ double keep[kRT];  // 1: column i from M W, 0: from U W
+  W[tid / kRT][tid % kRT] = mb.Wev[tid];
+  if (tid < kRT) keep[tid] = mb.Fac[tid] > 0.0 ? 1.0 : 0.0;
+  __syncthreads();
+  for (int i = tid; i < I; i += 256) {
+    double m[kRT], u[kRT];
+#pragma unroll
+    for (int c = 0; c < kRT; ++c) {
+      m[c] = c < R ? mb.M[(int64_t)i * kRT + c] : 0.0;
+      u[c] = c < R ? mb.U[(int64_t)i * R + c] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kRT; ++c) {
+      if (c < R) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int r = 0; r < kRT; ++r) {
+          a = fma(m[r], W[r][c], a);
+          b = fma(u[r], W[r][c], b);
+        }
+        mb.M[(int64_t)i * kRT + c] = keep[c] != 0.0 ? a : b;
+      }
+    }
+  }
+}
+
 // One wave per (problem, mode); the register variant is sized for the largest
-// I_n and R_n of the set, the LDS variant takes what does not fit.
+// I_n and R_n of the set, the LDS variant takes what does not fit.  With the
+// keep tie-break on any problem of the set, its transform of M_n runs first.
 template <typename S>
 void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.N; });
+  bool keep = false;
+  for (int r = 0; r < ls.count; ++r) keep = keep || ls.host[r]->tiebreak_keep;
+  if (keep) hipLaunchKernelGGL(k_tiebreak<S>, dim3(grid), dim3(256), 0, s, b);
   int imax = 1, rmax = 1;
   for (int r = 0; r < ls.count; ++r)
     for (int n = 0; n < ls.host[r]->N; ++n) {

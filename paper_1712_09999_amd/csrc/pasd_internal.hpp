@@ -72,6 +72,7 @@ struct ModeBufs {
   double* Spart; // Gram partials [nblk][kRT][kRT]
   double* Wf;    // kRT x kRT SVT factor
   double* Wev;   // kRT x kRT eigenvectors of the last Gram (warm start)
+  double* Fac;   // kRT SVT weights f_i of the last eigensolve (f_i > 0: V_n keeps direction i)
   int mblocks;   // number of GEMM-M partial blocks
   int sblocks;   // number of Gram partial blocks
 };
@@ -95,6 +96,7 @@ struct Problem {
   double mu_max, rho, tol;
   int max_iter;
   int precision;
+  int tiebreak_keep;  // PASD_FLAG_TIEBREAK_KEEP
   double* hist;  // residual history [max_iter][N]
   // first block of every mode within this problem's grid, per kernel kind
   int kb[KB_COUNT][kMaxN + 1];

@@ -113,6 +113,8 @@ int validate_impl(const pasd_config* c) {
   if (c->max_iter < 1) return fail(PASD_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (c->precision != PASD_FP64 && c->precision != PASD_FP32 && c->precision != PASD_BF16_GEMM)
     return fail(PASD_ERR_INVALID_ARG, "unknown precision");
+  if (c->flags & ~(PASD_FLAG_NO_GRAPH | PASD_FLAG_TIEBREAK_KEEP))
+    return fail(PASD_ERR_INVALID_ARG, "unknown flag");
   return PASD_OK;
 }
 
@@ -121,7 +123,8 @@ struct Plan {
   Layout L;
   size_t off_T, off_D, off_sc, off_hist, off_prob;
   size_t off_Y[kMaxN], off_P[kMaxN], off_U[kMaxN], off_Us[kMaxN], off_Uf[kMaxN], off_UfT[kMaxN],
-      off_Mpart[kMaxN], off_M[kMaxN], off_Spart[kMaxN], off_Wf[kMaxN], off_Wev[kMaxN];
+      off_Mpart[kMaxN], off_M[kMaxN], off_Spart[kMaxN], off_Wf[kMaxN], off_Wev[kMaxN],
+      off_Fac[kMaxN];
   ModeGeom geom[kMaxN];
   int mblocks[kMaxN], sblocks[kMaxN];
   int64_t numel;
@@ -163,6 +166,7 @@ void make_plan(const pasd_config* c, Plan& p) {
     p.off_Spart[n] = p.L.add((size_t)p.sblocks[n] * kRT * kRT * 8);
     p.off_Wf[n] = p.L.add(kRT * kRT * 8);
     p.off_Wev[n] = p.L.add(kRT * kRT * 8);
+    p.off_Fac[n] = p.L.add(kRT * 8);
   }
 }
 
@@ -190,6 +194,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     m.Spart = reinterpret_cast<double*>(b + pl.off_Spart[n]);
     m.Wf = reinterpret_cast<double*>(b + pl.off_Wf[n]);
     m.Wev = reinterpret_cast<double*>(b + pl.off_Wev[n]);
+    m.Fac = reinterpret_cast<double*>(b + pl.off_Fac[n]);
     m.mblocks = pl.mblocks[n];
     m.sblocks = pl.sblocks[n];
     p.lam[n] = ctx->lam[n];
@@ -200,6 +205,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   p.tol = ctx->cfg.tol;
   p.max_iter = ctx->cfg.max_iter;
   p.precision = ctx->cfg.precision;
+  p.tiebreak_keep = (ctx->cfg.flags & PASD_FLAG_TIEBREAK_KEEP) != 0 ? 1 : 0;
   // per-mode block offsets of the mode-grouped kernels, and the fused-pass share
   for (int n = 0; n <= ctx->N; ++n)
     for (int k = 0; k < KB_COUNT; ++k) p.kb[k][n] = 0;
@@ -548,7 +554,7 @@ int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
   g_last_error.clear();
   if (!ctx || !dst) return fail(PASD_ERR_INVALID_ARG, "ctx or dst is NULL");
   const bool per_mode = q == PASD_Q_Y || q == PASD_Q_Z || q == PASD_Q_U || q == PASD_Q_P ||
-                        q == PASD_Q_UF || q == PASD_Q_WEV;
+                        q == PASD_Q_UF || q == PASD_Q_WEV || q == PASD_Q_FAC;
   if (per_mode && (index < 0 || index >= ctx->N)) return fail(PASD_ERR_INVALID_ARG, "mode index out of range");
   DeviceGuard guard(ctx->dev);
   const bool f64 = ctx->cfg.precision == PASD_FP64;
@@ -621,6 +627,15 @@ int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
                         on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
       return PASD_OK;
     }
+    case PASD_Q_FAC: {
+      double f[kRT];
+      const double* s = f64 ? ctx->pd.m[index].Fac : ctx->pf.m[index].Fac;
+      HIP_TRY(hipMemcpyAsync(f, s, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      HIP_TRY(hipMemcpy(dst, f, sizeof(double) * ctx->geom[index].R,
+                        on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+      return PASD_OK;
+    }
     case PASD_Q_SCALARS: {
       int rc = read_scalars(ctx);
       if (rc != PASD_OK) return rc;
@@ -639,7 +654,8 @@ int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
 int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device) {
   g_last_error.clear();
   if (!ctx || !src) return fail(PASD_ERR_INVALID_ARG, "ctx or src is NULL");
-  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_U || q == PASD_Q_P || q == PASD_Q_WEV;
+  const bool per_mode = q == PASD_Q_Y || q == PASD_Q_U || q == PASD_Q_P || q == PASD_Q_WEV ||
+                        q == PASD_Q_FAC;
   if (per_mode && (index < 0 || index >= ctx->N)) return fail(PASD_ERR_INVALID_ARG, "mode index out of range");
   DeviceGuard guard(ctx->dev);
   const bool f64 = ctx->cfg.precision == PASD_FP64;
@@ -706,6 +722,15 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
           w[r * kRT + c] = (r < R && c < R) ? in[r * R + c] : (r == c ? 1.0 : 0.0);
       double* d = f64 ? ctx->pd.m[index].Wev : ctx->pf.m[index].Wev;
       HIP_TRY(hipMemcpy(d, w, sizeof(w), hipMemcpyHostToDevice));
+      return PASD_OK;
+    }
+    case PASD_Q_FAC: {
+      const int R = ctx->geom[index].R;
+      double f[kRT] = {0};
+      HIP_TRY(hipMemcpy(f, src, sizeof(double) * R,
+                        on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+      double* d = f64 ? ctx->pd.m[index].Fac : ctx->pf.m[index].Fac;
+      HIP_TRY(hipMemcpy(d, f, sizeof(f), hipMemcpyHostToDevice));
       return PASD_OK;
     }
     case PASD_Q_SCALARS: {

@@ -31,9 +31,10 @@ ERR_STATE = -6
 
 FP64, FP32, BF16_GEMM = 0, 1, 2
 FLAG_NO_GRAPH = 1
+FLAG_TIEBREAK_KEEP = 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16_GEMM}
 
-Q_E, Q_Y, Q_Z, Q_X, Q_U, Q_P, Q_UF, Q_SCALARS, Q_D, Q_WEV = range(10)
+Q_E, Q_Y, Q_Z, Q_X, Q_U, Q_P, Q_UF, Q_SCALARS, Q_D, Q_WEV, Q_FAC = range(11)
 
 # enum pasd_kernel, in launch order
 KERNELS = ("gemm_m", "reduce_m", "qr", "gemm_p", "gram", "eig", "fused", "control")
@@ -131,7 +132,7 @@ def make_config(dims: Sequence[int], ranks: Sequence[int], lam: Optional[Sequenc
                 alpha: Optional[Sequence[float]] = None, mu0: float = 1e-4, mu_max: float = 1e10,
                 rho: float = 1.1, tol: float = 1e-5, max_iter: int = 1000,
                 precision="fp64", device: int = -1, stream: int = 0,
-                graphs: bool = True) -> Config:
+                graphs: bool = True, tiebreak: str = "pre") -> Config:
     c = Config()
     lib().pasd_config_init(ctypes.byref(c))
     c.order = len(dims)
@@ -150,7 +151,9 @@ def make_config(dims: Sequence[int], ranks: Sequence[int], lam: Optional[Sequenc
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     c.device = int(device)
     c.stream = int(stream) if stream else None
-    c.flags = 0 if graphs else FLAG_NO_GRAPH
+    if tiebreak not in ("pre", "keep"):
+        raise ValueError("tiebreak must be 'pre' or 'keep'")
+    c.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_TIEBREAK_KEEP if tiebreak == "keep" else 0)
     return c
 
 
@@ -174,7 +177,7 @@ class Solver:
     def __init__(self, T, ranks: Sequence[int], *, lam=None, alpha=None, mu0: float = 1e-4,
                  mu_max: float = 1e10, rho: float = 1.1, tol: float = 1e-5, max_iter: int = 1000,
                  precision="fp64", device: Optional[int] = None, stream: int = 0,
-                 graphs: bool = True):
+                 graphs: bool = True, tiebreak: str = "pre"):
         import torch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         sdt = torch.float64 if self.precision == FP64 else torch.float32
@@ -190,7 +193,7 @@ class Solver:
         self.torch_dtype = sdt
         self.np_dtype = _state_dtype(self.precision)
         self.cfg = make_config(self.dims, ranks, lam, alpha, mu0, mu_max, rho, tol, max_iter,
-                               self.precision, self.device, stream, graphs)
+                               self.precision, self.device, stream, graphs, tiebreak)
         h = ctypes.c_void_p()
         torch.cuda.synchronize(T.device)
         _check(lib().pasd_create(ctypes.byref(self.cfg), ctypes.c_void_p(T.data_ptr()), 1,
@@ -269,13 +272,14 @@ class Solver:
             Q_U: ((I, R), np.float64), Q_P: ((R, J), self.np_dtype),
             Q_UF: ((I, R), np.float64), Q_SCALARS: ((2,), np.float64),
             Q_D: (self.dims, self.np_dtype), Q_WEV: ((R, R), np.float64),
+            Q_FAC: ((R,), np.float64),
         }[quantity]
         out = np.empty(shape, dtype=dt)
         _check(lib().pasd_export(self.handle, quantity, index, out.ctypes.data_as(ctypes.c_void_p), 0))
         return out
 
     def import_(self, quantity: int, index: int, value: np.ndarray):
-        dt = np.float64 if quantity in (Q_U, Q_SCALARS, Q_WEV) else self.np_dtype
+        dt = np.float64 if quantity in (Q_U, Q_SCALARS, Q_WEV, Q_FAC) else self.np_dtype
         v = np.ascontiguousarray(value, dtype=dt)
         _check(lib().pasd_import(self.handle, quantity, index, v.ctypes.data_as(ctypes.c_void_p), 0))
 
@@ -286,6 +290,7 @@ class Solver:
             st[f"U{n}"] = self.export(Q_U, n)
             st[f"P{n}"] = self.export(Q_P, n)
             st[f"W{n}"] = self.export(Q_WEV, n)
+            st[f"F{n}"] = self.export(Q_FAC, n)
         return st
 
     def restore(self, st: dict):
@@ -295,6 +300,8 @@ class Solver:
             self.import_(Q_U, n, st[f"U{n}"])
             self.import_(Q_P, n, st[f"P{n}"])
             self.import_(Q_WEV, n, st[f"W{n}"])
+            if f"F{n}" in st:
+                self.import_(Q_FAC, n, st[f"F{n}"])
         self.import_(Q_SCALARS, 0, st["scalars"])
 
 

@@ -61,11 +61,20 @@ def test_defaults_follow_algorithm_1():
     (dict(tol=float("nan")), binding.ERR_INVALID_ARG),
     (dict(max_iter=0), binding.ERR_INVALID_ARG),
     (dict(precision=7), binding.ERR_INVALID_ARG),
+    (dict(tiebreak="keep"), 0),
 ])
 def test_validation_codes(kw, code):
     assert pasd.validate(_cfg(**kw)) == code
     if code != 0:
         assert binding.last_error() != ""
+
+
+def test_unknown_flag_rejected():
+    c = _cfg()
+    c.flags = 4
+    assert pasd.validate(c) == binding.ERR_INVALID_ARG
+    c.flags = binding.FLAG_NO_GRAPH | binding.FLAG_TIEBREAK_KEEP
+    assert pasd.validate(c) == 0
 
 
 def test_order_above_max_rejected():
