@@ -266,6 +266,23 @@ def main():
         out["solve"]["rse_vs_planted_fp64"] = _rel(res["fp64"]["X"], wl.L)
         out["solves_per_s"] = out["solve"]["fp32"]["solves_per_s"]
         _progress("full solves done")
+        # Procrustes tie-break of eq. (10): the default (pre-threshold P) against
+        # keeping U^k where V^k vanishes; recovery of the planted low-rank part
+        tb = {}
+        for name in ("c1", "c2"):
+            w = wl if name == "c2" else workloads.make_config("c1")
+            row = {}
+            for t in ("pre", "keep"):
+                sv = P.Solver(w.T, w.ranks, precision="fp64", tol=w.tol, max_iter=w.max_iter,
+                              device=0, tiebreak=t)
+                info = sv.solve()
+                X = sv.result()[0].cpu().numpy()
+                row[t] = {"iterations": info.iterations, "converged": bool(info.converged),
+                          "rse_vs_planted": _rel(X, w.L)}
+                sv.close()
+            tb[name] = row
+        out["solve"]["tiebreak_fp64"] = tb
+        _progress("tie-break comparison done")
 
     if not args.no_serving:
         out["serving"] = serving_bench(args.srv_requests, min(args.srv_sequential, args.srv_requests))
