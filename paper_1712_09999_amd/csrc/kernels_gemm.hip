@@ -18,6 +18,7 @@
 // in LDS within a block and across blocks by a separate, fixed-order pass, so
 // results are bitwise reproducible.
 #include <algorithm>
+#include <type_traits>
 
 #include "pasd_internal.hpp"
 
@@ -308,7 +309,71 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   __shared__ double red[kMWaves][64][4];
   double* __restrict__ out = mb.Mpart + (int64_t)blk * g.I * g.R;  // [I][R] partial
 
-  if (g.B > 1) {
+  const int64_t csteps = (g.J + 15) / 16;
+  const int64_t cper = (csteps + mb.mblocks - 1) / mb.mblocks;
+  if (g.B > 1 && (g.B % 4) == 0 && (g.J % 4) == 0 && min(csteps, (int64_t)(blk + 1) * cper) <= g.J / 16) {
+    // Column scheme, rows split over the waves: every 16-column step of the
+    // block is full and 4-aligned.  Wave w owns row blocks rb0, rb0 + 1 (16
+    // rows each; passes of 16 row blocks) and runs through all of the block's
+    // steps, 4 at a time, so each lane reads 64 contiguous bytes of its row per
+    // tensor and every row is read in 256-byte runs; no cross-wave reduction.
+    constexpr int RBW = 2, KS = 4;
+    const int64_t sbeg = (int64_t)blk * cper;
+    const int64_t send = min(csteps, sbeg + cper);
+    const int nib = (g.I + 15) / 16;
+    const bool j32 = g.J < (int64_t(1) << 31);
+    const FastDiv fdb = pb.fd_b[n];
+    const int pr = min(p, g.R - 1);  // lanes p >= R read row R-1 (cached) and mask it
+    for (int rg = 0; rg < nib; rg += RBW * kMWaves) {
+      const int rb0 = rg + RBW * wave;
+      Acc acc[RBW];
+#pragma unroll
+      for (int u = 0; u < RBW; ++u) acc[u] = Acc{0, 0, 0, 0};
+      auto step = [&](int64_t st0, auto kcount) {
+        constexpr int K = decltype(kcount)::value;
+        V pv[K], dv[RBW][K], yv[RBW][K];
+#pragma unroll
+        for (int ks = 0; ks < K; ++ks) {
+          const int64_t j4 = (st0 + ks) * 16 + 4 * q;
+          const int64_t a = j32 ? (int64_t)fastdiv((uint32_t)j4, fdb) : j4 / g.B;
+          const int64_t b = j4 - a * g.B;
+          const S* dp = pb.D + a * (int64_t)g.I * g.B + b;
+          const S* yp = mb.Y + a * (int64_t)g.I * g.B + b;
+          pv[ks] = gld<V>(mb.P + (int64_t)pr * g.J + j4);
+#pragma unroll
+          for (int u = 0; u < RBW; ++u) {
+            const int64_t i = min((rb0 + u) * 16 + p, g.I - 1);
+            dv[u][ks] = gld<V>(dp + i * g.B);
+            yv[u][ks] = gld<V>(yp + i * g.B);
+          }
+        }
+        // every load of the steps is in flight before the first use
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < K; ++ks) {
+          const V pvv = p < g.R ? pv[ks] : V{0, 0, 0, 0};
+#pragma unroll
+          for (int u = 0; u < RBW; ++u) {
+            const bool ok = (rb0 + u) * 16 + p < g.I;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              acc[u] = MM<S>::mma(opnd<BF>(ok ? dv[u][ks][t] + yv[u][ks][t] * inv_mu : S(0)),
+                                  opnd<BF>(pvv[t]), acc[u]);
+          }
+        }
+      };
+      int64_t st = sbeg;
+      for (; st + KS <= send; st += KS) step(st, std::integral_constant<int, KS>{});
+      for (; st < send; ++st) step(st, std::integral_constant<int, 1>{});
+#pragma unroll
+      for (int u = 0; u < RBW; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = (rb0 + u) * 16 + MM<S>::row(q, v);
+          if (i < g.I && p < g.R) out[(int64_t)i * g.R + p] = (double)acc[u][v];
+        }
+    }
+  } else if (g.B > 1) {
     constexpr int IBP = sizeof(S) == 4 ? 8 : 4;  // row blocks per pass (register budget)
     const int64_t nsteps = (g.J + 15) / 16;
     const int64_t per_blk = (nsteps + mb.mblocks - 1) / mb.mblocks;
