@@ -639,11 +639,14 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
   // (lanes p >= R read row R-1, in cache anyway, and use zero)
   const bool pok = p < g.R;
   const S* prow = mb.P + (int64_t)min(p, g.R - 1) * g.J + 4 * q;
-  int64_t st = sbeg + wave;
-  for (; st + 4 * (kGramU - 1) < full_end; st += 4 * kGramU) {
+  // batches of 32 steps: the wave takes two runs of 4 consecutive steps, so
+  // every row of P_n is read in 256-byte pieces
+  int64_t bst = sbeg;
+  for (; bst + 4 * kGramU <= full_end; bst += 4 * kGramU) {
     V v[kGramU];
 #pragma unroll
-    for (int u = 0; u < kGramU; ++u) v[u] = *reinterpret_cast<const V*>(prow + (st + 4 * u) * 16);
+    for (int u = 0; u < kGramU; ++u)
+      v[u] = *reinterpret_cast<const V*>(prow + (bst + 16 * (u >> 2) + 4 * wave + (u & 3)) * 16);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < kGramU; ++u)
@@ -653,6 +656,7 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
         acc = mma64(x, x, acc);
       }
   }
+  int64_t st = bst + wave;
   for (; st < full_end; st += 4) {
     const V v = *reinterpret_cast<const V*>(prow + st * 16);
 #pragma unroll
