@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 
 constexpr int kMWaves = 8;
 
-template <typename S, bool BF>
+template <typename S, bool BF, bool RS>
 __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
   typedef typename MM<S>::vec_t V;
@@ -311,7 +311,13 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
 
   const int64_t csteps = (g.J + 15) / 16;
   const int64_t cper = (csteps + mb.mblocks - 1) / mb.mblocks;
-  if (g.B > 1 && (g.B % 4) == 0 && (g.J % 4) == 0 && min(csteps, (int64_t)(blk + 1) * cper) <= g.J / 16) {
+  // RS (the instantiation for a launch of one problem): with fewer than 12 row
+  // blocks most waves would own no rows and with fewer than 8 steps per block
+  // the split over steps below needs fewer round trips, so those take it; a
+  // batch of many problems (serving) uses the other instantiation, where the
+  // split over steps measured faster.
+  if (RS && g.B > 1 && (g.B % 4) == 0 && (g.J % 4) == 0 && cper >= 8 && g.I > 11 * 16 &&
+      min(csteps, (int64_t)(blk + 1) * cper) <= g.J / 16) {
     // Column scheme, rows split over the waves: every 16-column step of the
     // block is full and 4-aligned.  Wave w owns row blocks rb0, rb0 + 1 (16
     // rows each; passes of 16 row blocks) and runs through all of the block's
@@ -749,13 +755,20 @@ template <typename S>
 void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_M); });
+  const bool one = ls.count == 1;
   if constexpr (sizeof(S) == 4) {
     if (bf16_set(ls)) {
-      hipLaunchKernelGGL((k_gemm_m<S, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+      if (one)
+        hipLaunchKernelGGL((k_gemm_m<S, true, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+      else
+        hipLaunchKernelGGL((k_gemm_m<S, true, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
       return;
     }
   }
-  hipLaunchKernelGGL((k_gemm_m<S, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+  if (one)
+    hipLaunchKernelGGL((k_gemm_m<S, false, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+  else
+    hipLaunchKernelGGL((k_gemm_m<S, false, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
 }
 
 template <typename S>
