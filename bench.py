@@ -150,6 +150,50 @@ def serving_bench(count, seq_count):
     }
 
 
+def phase_bench(rs, rhos, trials, dim=100, seed0=17125000):
+    """The phase-transition workload of Fig. 1 (Section 5.1) as one batch of
+    solves through the serving loop: dim^3 tensors, Tucker rank r in every mode
+    (N(0, 1) core, Haar factors, left unscaled), a fraction rho of the entries
+    plus U(-1, 1), R_n = floor(1.2 r), epsilon 1e-5, maxiter 1000, FP64; a
+    trial succeeds when RSE = ||X - L|| / ||L|| <= 1e-3.  Returns the success
+    fraction per (rho, r) cell and the batched solve rate."""
+    import torch
+
+    from workloads.torch_gen import tucker_on_device
+    from paper_1712_09999_amd import serving
+
+    t0 = time.perf_counter()
+    reqs, cells, planted = [], [], []
+    for a, rho in enumerate(rhos):
+        for b, r in enumerate(rs):
+            for t in range(trials):
+                seed = seed0 + 100000 * t + 1000 * a + b
+                T, L, _ = tucker_on_device((dim,) * 3, (r,) * 3, rho, seed, value_range=(-1.0, 1.0),
+                                           dtype=torch.float64, scale=None)
+                reqs.append(serving.Request(len(reqs), 0.0, T, (int(1.2 * r),) * 3, tol=1e-5,
+                                            max_iter=1000))
+                cells.append((a, b))
+                planted.append(L)
+    torch.cuda.synchronize()
+    _progress(f"phase: {len(reqs)} tensors drawn in {time.perf_counter() - t0:.1f} s")
+    srv = serving.Server(precision="fp64", max_slots=64, step_iters=4, keep_results=True)
+    res = srv.run(reqs, realtime=False)
+    wall = srv.stats["wall_s"]
+    ok = [[0] * len(rs) for _ in rhos]
+    iters = 0
+    for q in res:
+        a, b = cells[q.rid]
+        L = planted[q.rid]
+        rse = float(torch.linalg.vector_norm(q.X - L) / torch.linalg.vector_norm(L))
+        ok[a][b] += int(rse <= 1e-3)
+        iters += q.iterations
+    _progress(f"phase: {len(res)} solves in {wall:.1f} s")
+    return {"dims": [dim] * 3, "r": list(rs), "rho": list(rhos), "trials": trials,
+            "precision": "fp64", "success": [[c / trials for c in row] for row in ok],
+            "solves": len(res), "iterations": iters, "wall_s": round(wall, 2),
+            "solves_per_s": round(len(res) / wall, 2), "iters_per_s": round(iters / wall, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +205,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--srv-requests", type=int, default=512)
     ap.add_argument("--srv-sequential", type=int, default=128)
+    ap.add_argument("--no-phase", action="store_true")
+    ap.add_argument("--phase-full", action="store_true",
+                    help="the full Fig. 1 grid (r = 2..50 and rho = 2..50%% in steps of 2, "
+                         "--phase-trials each) instead of every fourth point")
+    ap.add_argument("--phase-trials", type=int, default=1)
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (3 times), the "
                          "reference kernel that scales hardware traffic counters to bytes")
@@ -286,6 +335,12 @@ def main():
 
     if not args.no_serving:
         out["serving"] = serving_bench(args.srv_requests, min(args.srv_sequential, args.srv_requests))
+
+    if not args.no_phase:
+        step = 1 if args.phase_full else 4
+        rs = list(range(2, 51, 2))[::step]
+        rhos = [round(0.02 * k, 2) for k in range(1, 26)][::step]
+        out["phase_transition"] = phase_bench(rs, rhos, args.phase_trials)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(T64, ranks, args.cpu_iters)

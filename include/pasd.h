@@ -39,7 +39,8 @@ extern "C" {
 #endif
 
 #define PASD_MAX_ORDER 8   /* largest tensor order N supported */
-#define PASD_MAX_RANK 16   /* largest R_n supported */
+#define PASD_MAX_RANK 64   /* largest R_n supported; I_n R_n <= 8192 for R_n <= 16
+                              and I_n R_n <= 16384 above (QR workspace) */
 
 enum pasd_status {
   PASD_OK = 0,

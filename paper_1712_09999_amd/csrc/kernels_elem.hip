@@ -37,7 +37,8 @@ __device__ __forceinline__ double recon1(const Problem<S>& pb, int n, int64_t x)
   const int i = (int)(rem / g.B);
   const int64_t j = a * g.B + (rem - (int64_t)i * g.B);
   for (int r = 0; r < g.R; ++r)
-    z = fma((double)mb.Uf[(int64_t)i * kRT + r], (double)mb.P[(int64_t)r * g.J + j], z);
+    z = fma((double)mb.Uf[((int64_t)(r / kRT) * g.I + i) * kRT + r % kRT],
+            (double)mb.P[(int64_t)r * g.J + j], z);
   return z;
 }
 
@@ -157,6 +158,7 @@ struct FusedView {
   const S* P[NN];
   const S* F[NN];  // U_n W_n (rows of kRT) for n < N-1, its transpose for the last mode
   IT J[NN], I[NN], B[NN], Rb[NN];
+  int NT[NN];      // rank tiles (the tile-looped rank path)
   IT IN, Q, nchunk;
   FastDiv fq, frb[NN], fi[NN];
 };
@@ -179,6 +181,7 @@ __device__ __forceinline__ FusedView<S, NN, IT> fused_view(const Problem<S>& pb)
     v.I[n] = (IT)pb.g[n].I;
     v.B[n] = (IT)pb.g[n].B;
     v.Rb[n] = (IT)(pb.g[n].B / pb.g[NN - 1].I);
+    v.NT[n] = pb.g[n].T;
     v.frb[n] = pb.fd_rb[n];
     v.fi[n] = pb.fd_i[n];
   }
@@ -190,43 +193,96 @@ __device__ __forceinline__ FusedView<S, NN, IT> fused_view(const Problem<S>& pb)
 // and U_n W_n zero columns).  A scheduling barrier after the loads keeps them
 // issued together: left alone, the compiler interleaves loads and FMAs to save
 // registers and waits on each load in turn.
-template <typename S, typename ZT, int NN, int VEC, int RP, typename IT>
-__device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
-                                          ZT z[VEC]) {
+// RP = 0: ranks beyond one tile, a loop over the mode's T rank tiles with the
+// tile's 16 ranks unrolled (U_n W_n tile-major: tile t of row in_n at
+// (t I_n + in_n) kRT).
+template <typename S, typename ZT, int NN, int VEC, typename IT>
+__device__ __forceinline__ void recon_row_tiles(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
+                                                ZT z[VEC]) {
 #pragma unroll
   for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
+  const int T = v.NT[n];
   if (n == NN - 1) {
-    S pr[RP];
-    S u[RP][VEC];
+    for (int tt = 0; tt < T; ++tt) {
+      S pr[kRT];
+      S u[kRT][VEC];
 #pragma unroll
-    for (int r = 0; r < RP; ++r) {
-      gload<S, 1, IT>(v.P[n], (IT)r * v.J[n] + row, &pr[r]);
-      gload<S, VEC, IT>(v.F[n], (IT)r * v.IN + i, u[r]);
+      for (int r = 0; r < kRT; ++r) {
+        const IT rr = (IT)(tt * kRT + r);
+        gload<S, 1, IT>(v.P[n], rr * v.J[n] + row, &pr[r]);
+        gload<S, VEC, IT>(v.F[n], rr * v.IN + i, u[r]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < kRT; ++r)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r][t], (ZT)pr[r], z[t]);
     }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < RP; ++r)
-#pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r][t], (ZT)pr[r], z[t]);
   } else {
     const IT q1 = div_fixed<IT>(row, v.Rb[n], v.frb[n]);
     const IT a = n == 0 ? IT(0) : div_fixed<IT>(q1, v.I[n], v.fi[n]);  // A_0 = 1
     const IT in = q1 - a * v.I[n];
     const IT j = a * v.B[n] + (row - q1 * v.Rb[n]) * v.IN + i;
-    constexpr int W = VW<S>::n;  // U_n W_n rows are kRT long and 16-byte aligned
-    // U_n W_f rows are kRT wide and zero beyond R: read whole 16-byte vectors
-    constexpr int RU = (RP + W - 1) / W * W;
-    S u[RU];
+    constexpr int W = VW<S>::n;
+    for (int tt = 0; tt < T; ++tt) {
+      S u[kRT];
 #pragma unroll
-    for (int r = 0; r < RU; r += W) gload<S, W, IT>(v.F[n], in * (IT)kRT + (IT)r, &u[r]);
-    S pv[RP][VEC];
+      for (int r = 0; r < kRT; r += W)
+        gload<S, W, IT>(v.F[n], ((IT)tt * v.I[n] + in) * (IT)kRT + (IT)r, &u[r]);
+      S pv[kRT][VEC];
 #pragma unroll
-    for (int r = 0; r < RP; ++r) gload<S, VEC, IT>(v.P[n], (IT)r * v.J[n] + j, pv[r]);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int r = 0; r < kRT; ++r)
+        gload<S, VEC, IT>(v.P[n], (IT)(tt * kRT + r) * v.J[n] + j, pv[r]);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int r = 0; r < RP; ++r)
+      for (int r = 0; r < kRT; ++r)
 #pragma unroll
-      for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
+        for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
+    }
+  }
+}
+
+template <typename S, typename ZT, int NN, int VEC, int RP, typename IT>
+__device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
+                                          ZT z[VEC]) {
+  if constexpr (RP == 0) {
+    recon_row_tiles<S, ZT, NN, VEC, IT>(v, n, row, i, z);
+  } else {
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
+    if (n == NN - 1) {
+      S pr[RP];
+      S u[RP][VEC];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) {
+        gload<S, 1, IT>(v.P[n], (IT)r * v.J[n] + row, &pr[r]);
+        gload<S, VEC, IT>(v.F[n], (IT)r * v.IN + i, u[r]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < RP; ++r)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r][t], (ZT)pr[r], z[t]);
+    } else {
+      const IT q1 = div_fixed<IT>(row, v.Rb[n], v.frb[n]);
+      const IT a = n == 0 ? IT(0) : div_fixed<IT>(q1, v.I[n], v.fi[n]);  // A_0 = 1
+      const IT in = q1 - a * v.I[n];
+      const IT j = a * v.B[n] + (row - q1 * v.Rb[n]) * v.IN + i;
+      constexpr int W = VW<S>::n;  // U_n W_n rows are kRT long and 16-byte aligned
+      // U_n W_f rows are kRT wide and zero beyond R: read whole 16-byte vectors
+      constexpr int RU = (RP + W - 1) / W * W;
+      S u[RU];
+#pragma unroll
+      for (int r = 0; r < RU; r += W) gload<S, W, IT>(v.F[n], in * (IT)kRT + (IT)r, &u[r]);
+      S pv[RP][VEC];
+#pragma unroll
+      for (int r = 0; r < RP; ++r) gload<S, VEC, IT>(v.P[n], (IT)r * v.J[n] + j, pv[r]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < RP; ++r)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
+    }
   }
 }
 
@@ -408,8 +464,10 @@ __global__ void __launch_bounds__(256) k_init_small(Problem<S> pb, double mu0) {
   const int n = blockIdx.x;
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
-  for (int e = threadIdx.x; e < g.I * kRT; e += blockDim.x) {
-    const int i = e / kRT, c = e - i * kRT;
+  for (int e = threadIdx.x; e < g.I * g.T * kRT; e += blockDim.x) {
+    // Us tile-major: tile t, row i, column kRT t + cc
+    const int t = e / (g.I * kRT), rem = e - t * g.I * kRT;
+    const int i = rem / kRT, c = t * kRT + rem % kRT;
     const double v = (i == c && c < g.R) ? 1.0 : 0.0;
     if (c < g.R) mb.U[(int64_t)i * g.R + c] = v;
     mb.Us[e] = (S)v;
@@ -472,8 +530,8 @@ static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {
   for (int r = 0; r < ls.count; ++r) idx32 = idx32 && ls.host[r]->idx32;
   if (idx32)
     hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t>), dim3(grid), dim3(256), 0, s, b);
-  else  // offsets beyond 32 bits: 64-bit indexing, full rank tile
-    hipLaunchKernelGGL((k_fused<S, NN, kRT, uint64_t>), dim3(grid), dim3(256), 0, s, b);
+  else  // offsets beyond 32 bits: 64-bit indexing, full rank tile (or the tile loop)
+    hipLaunchKernelGGL((k_fused<S, NN, RP == 0 ? 0 : kRT, uint64_t>), dim3(grid), dim3(256), 0, s, b);
 }
 
 // The rank loop is unrolled to the largest R_n of the set, rounded up to even
@@ -509,16 +567,32 @@ static void fused_n(const LaunchSet<S>& ls, hipStream_t s) {
 }
 
 // All problems of a set have the same order N (the batch driver groups them).
+// Problems with some R_n > kRT take the tile-looped rank path (RP = 0).
 template <typename S>
 void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
-  switch (ls.host[0]->N) {
-    case 2: fused_n<S, 2>(ls, s); break;
-    case 3: fused_n<S, 3>(ls, s); break;
-    case 4: fused_n<S, 4>(ls, s); break;
-    case 5: fused_n<S, 5>(ls, s); break;
-    case 6: fused_n<S, 6>(ls, s); break;
-    case 7: fused_n<S, 7>(ls, s); break;
-    default: fused_n<S, 8>(ls, s); break;
+  LaunchSet<S> nar, wid;
+  split_wide(ls, nar, wid);
+  if (nar.count) {
+    switch (nar.host[0]->N) {
+      case 2: fused_n<S, 2>(nar, s); break;
+      case 3: fused_n<S, 3>(nar, s); break;
+      case 4: fused_n<S, 4>(nar, s); break;
+      case 5: fused_n<S, 5>(nar, s); break;
+      case 6: fused_n<S, 6>(nar, s); break;
+      case 7: fused_n<S, 7>(nar, s); break;
+      default: fused_n<S, 8>(nar, s); break;
+    }
+  }
+  if (wid.count) {
+    switch (wid.host[0]->N) {
+      case 2: fused_idx<S, 2, 0>(wid, s); break;
+      case 3: fused_idx<S, 3, 0>(wid, s); break;
+      case 4: fused_idx<S, 4, 0>(wid, s); break;
+      case 5: fused_idx<S, 5, 0>(wid, s); break;
+      case 6: fused_idx<S, 6, 0>(wid, s); break;
+      case 7: fused_idx<S, 7, 0>(wid, s); break;
+      default: fused_idx<S, 8, 0>(wid, s); break;
+    }
   }
 }
 

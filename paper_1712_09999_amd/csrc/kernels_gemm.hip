@@ -705,6 +705,97 @@ __global__ void __launch_bounds__(256) k_gram(Batch<S> bt) {
 // Host launchers
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// The Gram partials of a problem with some R_n > kRT: S_n = P_n P_n^T with P_n
+// of T rank tiles, tile pair (a, b), a <= b, on FP64 MFMAs whose operands are
+// the same lane fragments as in k_gram (lane (p, q) holds row kRT t + p at
+// columns 4 q .. 4 q + 3 of the 16-column step), so tile a's fragment is A and
+// tile b's is B.  Wave w takes steps w, w + 4, ...; the waves' sums are added
+// in LDS in a fixed order, one tile pair at a time; the partial is RT x RT with
+// both triangles written.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_gram_w(Batch<S> bt) {
+  typedef typename MM<S>::vec_t V;
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done) return;
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_GRAM], pb.N, lb);
+  const int blk = lb - pb.kb[KB_GRAM][n];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int T = g.T, RT = T * kRT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  __shared__ double red[4][64][4];
+  const int64_t nsteps = (g.J + 15) / 16;
+  const int64_t per_blk = (nsteps + mb.sblocks - 1) / mb.sblocks;
+  const int64_t sbeg = (int64_t)blk * per_blk;
+  const int64_t send = min(nsteps, sbeg + per_blk);
+  const bool pvec = (g.J % 4) == 0;
+  constexpr int kPairs = kMaxTiles * (kMaxTiles + 1) / 2;
+  d4v acc[kPairs];
+#pragma unroll
+  for (int e = 0; e < kPairs; ++e) acc[e] = d4v{0, 0, 0, 0};
+  const S* prow[kMaxTiles];
+  bool pok[kMaxTiles];
+#pragma unroll
+  for (int t = 0; t < kMaxTiles; ++t) {
+    const int row = kRT * t + p;
+    pok[t] = t < T && row < g.R;
+    prow[t] = mb.P + (int64_t)min(row, g.R - 1) * g.J;
+  }
+  for (int64_t st = sbeg + wave; st < send; st += 4) {
+    const int64_t j4 = st * 16 + 4 * q;
+    const bool full = pvec && st * 16 + 16 <= g.J;
+    double x[kMaxTiles][4];
+#pragma unroll
+    for (int t = 0; t < kMaxTiles; ++t) {
+      if (full) {
+        const V v = *reinterpret_cast<const V*>(prow[t] + j4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[t][u] = (double)v[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[t][u] = j4 + u < g.J ? (double)prow[t][j4 + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[t][u] = pok[t] ? x[t][u] : 0.0;
+    }
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxTiles; ++a)
+#pragma unroll
+      for (int b = a; b < kMaxTiles; ++b, ++e)
+        if (b < T) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acc[e] = mma64(x[a][u], x[b][u], acc[e]);
+        }
+  }
+  double* out = mb.Spart + (int64_t)blk * RT * RT;
+  int e = 0;
+#pragma unroll
+  for (int a = 0; a < kMaxTiles; ++a)
+#pragma unroll
+    for (int b = a; b < kMaxTiles; ++b, ++e) {
+      if (b >= T) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[wave][lane][v] = acc[e][v];
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double sm = red[0][lane][v] + red[1][lane][v] + red[2][lane][v] + red[3][lane][v];
+          const int r = kRT * a + MM<double>::row(q, v), c = kRT * b + p;
+          out[(int64_t)r * RT + c] = sm;  // S[r][c]
+          if (a != b) out[(int64_t)c * RT + r] = sm;
+        }
+      }
+      __syncthreads();
+    }
+}
+
 int gemm_m_blocks(const ModeGeom& g, int N) {
   // one block of 8 waves per compute unit across the N modes of a solve (a
   // block holds its CU's register file), capped by the available K-steps
@@ -715,9 +806,10 @@ int gemm_m_blocks(const ModeGeom& g, int N) {
 }
 
 int gram_blocks(const ModeGeom& g) {
-  // at most 64: the eigensolver loads every partial in one pass
+  // at most 64: the eigensolver loads every partial in one pass; 16 with more
+  // than one rank tile (partials of RT x RT)
   const int64_t steps = (g.J + 15) / 16;
-  int64_t want = 64;
+  int64_t want = g.T > 1 ? 16 : 64;
   int64_t maxb = (steps + 3) / 4;
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }
@@ -738,8 +830,31 @@ static bool bf16_set(const LaunchSet<S>& ls) {
   return sizeof(S) == 4 && ls.host[0]->precision == PASD_BF16_GEMM;
 }
 
+// The unfolding GEMMs and the GEMM-M reduction work on one rank tile: a
+// problem with some R_n > kRT enters as its tile views.  A set longer than
+// kMaxBatch goes out in several launches.
+template <typename S, typename F>
+static void for_tile_sets(const LaunchSet<S>& ls, F launch) {
+  LaunchSet<S> out;
+  out.count = 0;
+  for (int r = 0; r < ls.count; ++r) {
+    const Problem<S>* h = ls.host[r];
+    const int nv = h->wide ? h->ntiles : 1;
+    for (int t = 0; t < nv; ++t) {
+      if (out.count == kMaxBatch) {
+        launch(out);
+        out.count = 0;
+      }
+      out.host[out.count] = h->wide ? h->view_host[t] : h;
+      out.dev[out.count] = h->wide ? h->view_dev[t] : ls.dev[r];
+      ++out.count;
+    }
+  }
+  if (out.count) launch(out);
+}
+
 template <typename S>
-void launch_gemm_p(const LaunchSet<S>& ls, hipStream_t s) {
+static void launch_gemm_p_set(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_P); });
   if constexpr (sizeof(S) == 4) {
@@ -752,7 +867,13 @@ void launch_gemm_p(const LaunchSet<S>& ls, hipStream_t s) {
 }
 
 template <typename S>
-void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
+void launch_gemm_p(const LaunchSet<S>& ls, hipStream_t s) {
+  if (ls.count <= kMaxBatch && !any_wide(ls)) return launch_gemm_p_set(ls, s);
+  for_tile_sets(ls, [s](const LaunchSet<S>& t) { launch_gemm_p_set(t, s); });
+}
+
+template <typename S>
+static void launch_gemm_m_set(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_M); });
   const bool one = ls.count == 1;
@@ -772,17 +893,37 @@ void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
 }
 
 template <typename S>
-void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s) {
+void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
+  if (ls.count <= kMaxBatch && !any_wide(ls)) return launch_gemm_m_set(ls, s);
+  for_tile_sets(ls, [s](const LaunchSet<S>& t) { launch_gemm_m_set(t, s); });
+}
+
+template <typename S>
+static void launch_reduce_m_set(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_REDUCE_M); });
   hipLaunchKernelGGL(k_reduce_m<S>, dim3(tot), dim3(256), 0, s, b);
 }
 
 template <typename S>
+void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s) {
+  if (ls.count <= kMaxBatch && !any_wide(ls)) return launch_reduce_m_set(ls, s);
+  for_tile_sets(ls, [s](const LaunchSet<S>& t) { launch_reduce_m_set(t, s); });
+}
+
+template <typename S>
 void launch_gram(const LaunchSet<S>& ls, hipStream_t s) {
+  LaunchSet<S> nar, wid;
+  split_wide(ls, nar, wid);
   Batch<S> b;
-  const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
-  hipLaunchKernelGGL(k_gram<S>, dim3(tot), dim3(256), 0, s, b);
+  if (nar.count) {
+    const int tot = make_batch(nar, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
+    hipLaunchKernelGGL(k_gram<S>, dim3(tot), dim3(256), 0, s, b);
+  }
+  if (wid.count) {
+    const int tot = make_batch(wid, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
+    hipLaunchKernelGGL(k_gram_w<S>, dim3(tot), dim3(256), 0, s, b);
+  }
 }
 
 #define INST(S)                                                         \

@@ -203,7 +203,8 @@ __device__ __forceinline__ double rcp_nr(double a) {
 // |a_pq| > thr sqrt(|a_pp a_qq|), compared in squares, and |a_pq| > 1e-150 so
 // that the squares below stay normal.  (A matrix below that scale has every
 // singular value far under the threshold tau: its SVT factor is zero.)
-__device__ __forceinline__ bool jacobi_needed(const double (*A)[kRT + 1], int p, int q, double thr) {
+template <int LD>
+__device__ __forceinline__ bool jacobi_needed(const double (*A)[LD], int p, int q, double thr) {
   const double b = fabs(A[p][q]);
   return b > 1e-150 && b * b > thr * thr * fabs(A[p][p]) * fabs(A[q][q]);
 }
@@ -914,11 +915,306 @@ __global__ void __launch_bounds__(256) k_tiebreak(Batch<S> bt) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Rank-wide variants (some R_n > kRT; factors stored tile-major, RT = T kRT).
+// These carry the same arithmetic as the one-tile kernels with every rank
+// index running to R_n <= PASD_MAX_RANK.
+// ---------------------------------------------------------------------------
+constexpr int kQrLdsW = 16384;  // doubles of LDS for M when R_n > kRT (I_n * R_n <= 16384)
+constexpr int kMR = PASD_MAX_RANK;
+
+// Sum over the 256 threads of a block in a fixed order (red: 4 doubles of LDS).
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return s;
+}
+
+// Householder QR of M_n (I x R, column-major in LDS) by a 256-thread block, the
+// same reflectors as k_qr (LAPACK dgeqr2 / dorg2r conventions): wave w applies
+// the reflector of a column step to columns c + 1 + w, c + 5, ..., each one a
+// wave-wide dot product followed by its update, so the waves need no barrier
+// between the two.
+template <typename S>
+__global__ void __launch_bounds__(256) k_qr_w(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int n = blockIdx.x - bt.start[req];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int I = g.I, R = g.R, T = g.T, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  __shared__ double A[kQrLdsW];  // column-major A[c * I + i]
+  __shared__ double tau[kMR];
+  __shared__ double red[4];
+  for (int e = tid; e < I * R; e += 256) {
+    const int c = e / I, i = e - c * I;
+    A[e] = mb.M[((int64_t)(c / kRT) * I + i) * kRT + c % kRT];
+  }
+  __syncthreads();
+  for (int c = 0; c < R; ++c) {
+    double part = 0;
+    for (int i = c + 1 + tid; i < I; i += 256) {
+      const double x = A[c * I + i];
+      part += x * x;
+    }
+    const double xnorm2 = block_sum256(part, red);
+    const double alpha = A[c * I + c];
+    double t = 0, beta = alpha, scale = 0;
+    if (xnorm2 > 0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    if (xnorm2 > 0)
+      for (int i = c + 1 + tid; i < I; i += 256) A[c * I + i] *= scale;
+    __syncthreads();
+    for (int j = c + 1 + wave; j < R; j += 4) {
+      double d = 0;
+      for (int i = c + 1 + lane; i < I; i += 64) d += A[c * I + i] * A[j * I + i];
+      d = wave_sum(d) + A[j * I + c];
+      if (t != 0) {
+        for (int i = c + 1 + lane; i < I; i += 64) A[j * I + i] -= t * d * A[c * I + i];
+        if (lane == 0) A[j * I + c] -= t * d;
+      }
+    }
+    if (tid == 0) {
+      A[c * I + c] = beta;
+      tau[c] = t;
+    }
+    __syncthreads();
+  }
+  for (int c = R - 1; c >= 0; --c) {
+    const double t = tau[c];
+    for (int j = c + 1 + wave; j < R; j += 4) {
+      double d = 0;
+      for (int i = c + 1 + lane; i < I; i += 64) d += A[c * I + i] * A[j * I + i];
+      d = wave_sum(d) + A[j * I + c];
+      for (int i = c + 1 + lane; i < I; i += 64) A[j * I + i] -= t * d * A[c * I + i];
+      if (lane == 0) A[j * I + c] -= t * d;
+    }
+    __syncthreads();
+    for (int i = c + 1 + tid; i < I; i += 256) A[c * I + i] = -t * A[c * I + i];
+    if (tid == 0) A[c * I + c] = 1.0 - t;
+    for (int i = tid; i < c; i += 256) A[c * I + i] = 0.0;
+    __syncthreads();
+  }
+  for (int e = tid; e < I * T * kRT; e += 256) {
+    const int t = e / (I * kRT), rem = e - t * I * kRT;
+    const int i = rem / kRT, c = t * kRT + rem % kRT;
+    const double v = c < R ? A[c * I + i] : 0.0;
+    if (c < R) mb.U[(int64_t)i * R + c] = v;
+    mb.Us[e] = (S)v;
+  }
+}
+
+// The keep tie-break transform of M_n (see k_tiebreak) for R_n up to kMR: rows
+// of M_n and U_n are staged in LDS 64 at a time, thread (row, column) forms
+// both candidates and keeps one.
+template <typename S>
+__global__ void __launch_bounds__(256) k_tiebreak_w(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (!pb.tiebreak_keep || pb.sc->done || pb.sc->k == 0) return;
+  const int n = blockIdx.x - bt.start[req];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int I = g.I, R = g.R, RT = g.T * kRT, tid = threadIdx.x;
+  __shared__ double W[kMR][kMR + 1];
+  __shared__ double keep[kMR];
+  __shared__ double Ml[64][kMR];
+  __shared__ double Ul[64][kMR];
+  for (int e = tid; e < RT * RT; e += 256) W[e / RT][e % RT] = mb.Wev[e];
+  for (int e = tid; e < RT; e += 256) keep[e] = mb.Fac[e] > 0.0 ? 1.0 : 0.0;
+  const int c = tid & 63;
+  for (int i0 = 0; i0 < I; i0 += 64) {
+    const int ni = min(64, I - i0);
+    __syncthreads();
+    for (int e = tid; e < ni * R; e += 256) {
+      const int il = e / R, r = e - il * R, i = i0 + il;
+      Ml[il][r] = mb.M[((int64_t)(r / kRT) * I + i) * kRT + r % kRT];
+      Ul[il][r] = mb.U[(int64_t)i * R + r];
+    }
+    __syncthreads();
+    if (c < R) {
+      for (int il = tid >> 6; il < ni; il += 4) {
+        double a = 0.0, b = 0.0;
+        for (int r = 0; r < R; ++r) {
+          a = fma(Ml[il][r], W[r][c], a);
+          b = fma(Ul[il][r], W[r][c], b);
+        }
+        mb.M[((int64_t)(c / kRT) * I + i0 + il) * kRT + c % kRT] = keep[c] != 0.0 ? a : b;
+      }
+    }
+  }
+}
+
+// The SVT factor for R_n up to kMR (steps of k_eig): the Gram from its
+// partials, the warm start S' = W0^T S W0, round-robin Jacobi sweeps until no
+// pair needs a rotation, then W_f = W diag(f) W^T and U W_f.  A round computes
+// the R'/2 rotations once (one thread per pair, into LDS), then every thread
+// applies them to its 2 x 2 blocks of the matrix (read from one buffer,
+// written to the other) and to its entries of the eigenvectors.
+template <typename S>
+__global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done) return;
+  const int n = blockIdx.x - bt.start[req];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int R = g.R, I = g.I, RT = g.T * kRT, tid = threadIdx.x;
+  const bool warm = pb.sc->k > 0;
+  __shared__ double Sb[2][kMR][kMR + 1];
+  __shared__ double W[kMR][kMR + 1];
+  __shared__ double T1[kMR][kMR + 1];
+  __shared__ double rot[kMR / 2][3];
+  __shared__ double fac[kMR];
+  const int nb = mb.sblocks;
+  for (int e = tid; e < RT * RT; e += 256) {
+    const int r = e / RT, c = e - r * RT;
+    const bool in = r < R && c < R;
+    double sm = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < nb; ++b) sm += mb.Spart[(int64_t)b * RT * RT + e];
+    Sb[0][r][c] = in ? sm : 0.0;
+    W[r][c] = (warm && in) ? mb.Wev[e] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < RT * RT; e += 256) {  // T1 = S W0, S from its upper triangle
+    const int r = e / RT, c = e - r * RT;
+    double t = 0;
+    for (int k = 0; k < R; ++k) t += (r <= k ? Sb[0][r][k] : Sb[0][k][r]) * W[k][c];
+    T1[r][c] = t;
+  }
+  __syncthreads();
+  for (int e = tid; e < RT * RT; e += 256) {  // S' = W0^T T1, symmetric by construction
+    const int r = e / RT, c = e - r * RT;
+    const int rr = r <= c ? r : c, cc = r <= c ? c : r;
+    double v = 0;
+    for (int k = 0; k < R; ++k) v += W[k][rr] * T1[k][cc];
+    Sb[1][r][c] = (r < R && c < R) ? v : 0.0;
+  }
+  __syncthreads();
+  const double thr = sizeof(S) == 4 ? 5.9604644775390625e-08 : 4.0e-16;
+  const int Rp = R + (R & 1);
+  const int half = Rp / 2;
+  const int m = Rp - 1;
+  int sweeps = 0;
+  int cur = 1;
+  for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
+    int need = 0;
+    for (int e = tid; e < R * R; e += 256) {
+      const int p = e / R, q = e - p * R;
+      if (p < q) need |= jacobi_needed(Sb[cur], p, q, thr) ? 1 : 0;
+    }
+    if (!__syncthreads_or(need)) break;
+    sweeps = sweep + 1;
+    for (int rd = 0; rd < m; ++rd) {
+      const double (*A)[kMR + 1] = Sb[cur];
+      double (*B)[kMR + 1] = Sb[cur ^ 1];
+      if (tid < half) {
+        int p, q;
+        rr_pair(rd, tid, m, p, q);
+        double c, sn, t;
+        jacobi_rotation(A[p][p], A[q][q], A[p][q], q < R, thr, c, sn, t);
+        rot[tid][0] = c;
+        rot[tid][1] = sn;
+        rot[tid][2] = t;
+      }
+      __syncthreads();
+      for (int e = tid; e < half * half; e += 256) {
+        const int k = e / half, l = e - k * half;
+        if (k > l) continue;
+        int pk, qk, pl, ql;
+        rr_pair(rd, k, m, pk, qk);
+        rr_pair(rd, l, m, pl, ql);
+        const double ck = rot[k][0], sk = rot[k][1], tk = rot[k][2];
+        const double cl = rot[l][0], sl = rot[l][1];
+        const double x00 = A[pk][pl], x01 = A[pk][ql], x10 = A[qk][pl], x11 = A[qk][ql];
+        const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
+        const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
+        double z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
+        double z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
+        if (k == l && sk != 0.0) {
+          const double tb = tk * x01;
+          z00 = x00 - tb;
+          z11 = x11 + tb;
+          z01 = 0.0;
+          z10 = 0.0;
+        }
+        B[pk][pl] = z00;
+        B[pk][ql] = z01;
+        B[qk][pl] = z10;
+        B[qk][ql] = z11;
+        B[pl][pk] = z00;
+        B[ql][pk] = z01;
+        B[pl][qk] = z10;
+        B[ql][qk] = z11;
+      }
+      for (int e = tid; e < R * half; e += 256) {
+        const int i = e / half, l = e - i * half;
+        int pl, ql;
+        rr_pair(rd, l, m, pl, ql);
+        const double cl = rot[l][0], sl = rot[l][1];
+        const double wp = W[i][pl], wq = W[i][ql];
+        W[i][pl] = cl * wp - sl * wq;
+        W[i][ql] = sl * wp + cl * wq;
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+  if (tid == 0) pb.sc->eig_sweeps[n] = sweeps;
+  const double tau = pb.lam[n] / pb.sc->mu;
+  if (tid < RT) {
+    double f = 0.0;
+    if (tid < R) {
+      const double l = Sb[cur][tid][tid];
+      const double sig = sqrt(l > 0.0 ? l : 0.0);
+      f = sig > tau ? (sig - tau) / sig : 0.0;
+    }
+    fac[tid] = f;
+    mb.Fac[tid] = f;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int cnt = __popcll(__ballot(tid < R && fac[tid] > 0.0));
+    if (tid == 0) pb.sc->rank[n] = cnt;
+  }
+  for (int e = tid; e < RT * RT; e += 256) {
+    const int r = e / RT, c = e - r * RT;
+    double sm = 0.0;
+    if (r < R && c < R)
+      for (int i = 0; i < R; ++i) sm += W[r][i] * fac[i] * W[c][i];
+    T1[r][c] = sm;
+    mb.Wf[e] = sm;
+    mb.Wev[e] = (r < R && c < R) ? W[r][c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  // U W_f: lane c is a column of the result, wave w takes rows w, w + 4, ...
+  const int c = tid & 63;
+  if (c < RT) {
+    for (int i = tid >> 6; i < I; i += 4) {
+      const double* urow = mb.U + (int64_t)i * R;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < R; ++k) acc = fma(urow[k], T1[k][c], acc);
+      mb.Uf[((int64_t)(c / kRT) * I + i) * kRT + c % kRT] = (S)acc;
+      mb.UfT[(int64_t)c * I + i] = (S)acc;
+    }
+  }
+}
+
 // One wave per (problem, mode); the register variant is sized for the largest
 // I_n and R_n of the set, the LDS variant takes what does not fit.  With the
 // keep tie-break on any problem of the set, its transform of M_n runs first.
 template <typename S>
-void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
+static void launch_qr_narrow(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.N; });
   bool keep = false;
@@ -956,10 +1252,33 @@ void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
 }
 
 template <typename S>
+void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
+  LaunchSet<S> nar, wid;
+  split_wide(ls, nar, wid);
+  if (nar.count) launch_qr_narrow(nar, s);
+  if (wid.count) {
+    Batch<S> b;
+    const int grid = make_batch(wid, b, [](const Problem<S>& p) { return p.N; });
+    bool keep = false;
+    for (int r = 0; r < wid.count; ++r) keep = keep || wid.host[r]->tiebreak_keep;
+    if (keep) hipLaunchKernelGGL(k_tiebreak_w<S>, dim3(grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_qr_w<S>, dim3(grid), dim3(256), 0, s, b);
+  }
+}
+
+template <typename S>
 void launch_eig(const LaunchSet<S>& ls, hipStream_t s) {
+  LaunchSet<S> nar, wid;
+  split_wide(ls, nar, wid);
   Batch<S> b;
-  const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.N; });
-  hipLaunchKernelGGL(k_eig<S>, dim3(grid), dim3(256), 0, s, b);
+  if (nar.count) {
+    const int grid = make_batch(nar, b, [](const Problem<S>& p) { return p.N; });
+    hipLaunchKernelGGL(k_eig<S>, dim3(grid), dim3(256), 0, s, b);
+  }
+  if (wid.count) {
+    const int grid = make_batch(wid, b, [](const Problem<S>& p) { return p.N; });
+    hipLaunchKernelGGL(k_eig_w<S>, dim3(grid), dim3(256), 0, s, b);
+  }
 }
 
 template void launch_qr<float>(const LaunchSet<float>&, hipStream_t);

@@ -10,6 +10,7 @@ namespace pasd {
 
 constexpr int kMaxN = PASD_MAX_ORDER;
 constexpr int kRT = 16;        // rank tile: R_n is padded to 16 in the factors and partials
+constexpr int kMaxTiles = PASD_MAX_RANK / kRT;  // rank tiles of the widest mode
 constexpr int kResSlots = 64;  // residual maxima are spread over this many words per mode
 constexpr int kXcds = 8;       // accelerator complex dies of gfx950; blocks are dealt to them in turn
 constexpr int kCUs = 256;      // compute units of the MI355X
@@ -38,6 +39,7 @@ __host__ __device__ inline uint32_t fastdiv(uint32_t n, FastDiv f) {
 struct ModeGeom {
   int64_t A, B, J;  // J = A*B
   int I, R;
+  int T;  // rank tiles, ceil(R / kRT); the factors are padded to T * kRT columns
 };
 
 // Device-resident control state of one context.
@@ -62,17 +64,20 @@ struct DevScalars {
 template <typename S>
 struct ModeBufs {
   S* Y;          // multiplier, numel
-  S* P;          // R x J (row-major)
+  // Rank-indexed factors with R > kRT are stored tile-major: T blocks, block t
+  // holding columns kRT t .. kRT t + kRT - 1 in the one-tile layout, so that a
+  // tile is itself a valid one-tile factor.  RT = T kRT below.
+  S* P;          // RT x J (row-major; rows >= R zero)
   double* U;     // I x R (row-major)  active subspace
-  S* Us;         // I x kRT  U in the state type, zero-padded columns (GEMM-P operand)
-  S* Uf;         // I x kRT  U W (SVT-folded factor), padded rows of 16
-  S* UfT;        // kRT x I  transposed copy (last mode uses it)
-  double* Mpart; // GEMM-M split-K partials [nblk][I][R] (double)
-  double* M;     // reduced M, I x kRT (columns >= R unused)
-  double* Spart; // Gram partials [nblk][kRT][kRT]
-  double* Wf;    // kRT x kRT SVT factor
-  double* Wev;   // kRT x kRT eigenvectors of the last Gram (warm start)
-  double* Fac;   // kRT SVT weights f_i of the last eigensolve (f_i > 0: V_n keeps direction i)
+  S* Us;         // [T][I][kRT]  U in the state type, zero-padded columns (GEMM-P operand)
+  S* Uf;         // [T][I][kRT]  U W (SVT-folded factor)
+  S* UfT;        // RT x I  transposed copy (last mode uses it)
+  double* Mpart; // GEMM-M split-K partials [T][nblk][I][R_t] (double), R_t = min(R - kRT t, kRT)
+  double* M;     // reduced M, [T][I][kRT] (columns >= R unused)
+  double* Spart; // Gram partials [nblk][RT][RT]
+  double* Wf;    // RT x RT SVT factor
+  double* Wev;   // RT x RT eigenvectors of the last Gram (warm start)
+  double* Fac;   // RT SVT weights f_i of the last eigensolve (f_i > 0: V_n keeps direction i)
   int mblocks;   // number of GEMM-M partial blocks
   int sblocks;   // number of Gram partial blocks
 };
@@ -110,6 +115,15 @@ struct Problem {
   FastDiv fd_i[kMaxN];
   // unfolding GEMMs: B_n, for column indices j < 2^31
   FastDiv fd_b[kMaxN];
+  // Some R_n > kRT: the rank-wide kernels run this problem.  The unfolding
+  // GEMMs and the GEMM-M reduction, which work on one rank tile, run it as
+  // `ntiles` views: view t is a copy whose mode n carries tile t alone (R_n
+  // replaced by R_t, the tile's factor pointers, no blocks where kRT t >= R_n).
+  // Host code only reads the view pointers.
+  int wide;
+  int ntiles;
+  const Problem* view_host[kMaxTiles];
+  const Problem* view_dev[kMaxTiles];
 };
 
 // One launch over up to kMaxBatch problems (kernel arguments, ~1.6 KB): block
@@ -163,6 +177,26 @@ struct LaunchSet {
   const Problem<S>* host[kMaxBatch];
   const Problem<S>* dev[kMaxBatch];
 };
+
+template <typename S>
+inline bool any_wide(const LaunchSet<S>& ls) {
+  for (int r = 0; r < ls.count; ++r)
+    if (ls.host[r]->wide) return true;
+  return false;
+}
+
+// Problems of a set with every R_n <= kRT, and those with some R_n > kRT.
+template <typename S>
+inline void split_wide(const LaunchSet<S>& ls, LaunchSet<S>& narrow, LaunchSet<S>& wide) {
+  narrow.count = 0;
+  wide.count = 0;
+  for (int r = 0; r < ls.count; ++r) {
+    LaunchSet<S>& d = ls.host[r]->wide ? wide : narrow;
+    d.host[d.count] = ls.host[r];
+    d.dev[d.count] = ls.dev[r];
+    ++d.count;
+  }
+}
 
 // Launchers of one iteration's kernels over a set (each enqueues on `s`;
 // kernels read sc->done of their problem and skip).

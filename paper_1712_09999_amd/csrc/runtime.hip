@@ -70,6 +70,8 @@ struct pasd_ctx {
   DevScalars* host_sc = nullptr;  // pinned host mirror
   Problem<float> pf;
   Problem<double> pd;
+  Problem<float> vf[kMaxTiles];  // rank-tile views (problems with some R_n > kRT)
+  Problem<double> vd[kMaxTiles];
   void* T = nullptr;
   void* scratch_out = nullptr;  // numel elements, for host exports
   // kGraphIters iterations captured once (on cap_stream) and replayed on `stream`
@@ -100,8 +102,9 @@ int validate_impl(const pasd_config* c) {
     if (R > PASD_MAX_RANK)
       return fail(PASD_ERR_UNSUPPORTED, "rank above " + std::to_string(PASD_MAX_RANK));
     if (c->dims[n] > (1 << 30)) return fail(PASD_ERR_UNSUPPORTED, "dimension too large");
-    if (c->dims[n] * R > 8192)
-      return fail(PASD_ERR_UNSUPPORTED, "I_n * R_n above 8192 (QR workspace)");
+    if (c->dims[n] * R > (R <= kRT ? 8192 : 16384))
+      return fail(PASD_ERR_UNSUPPORTED, R <= kRT ? "I_n * R_n above 8192 (QR workspace)"
+                                                 : "I_n * R_n above 16384 (QR workspace)");
     if (!isfinite(c->lambda[n]) || !isfinite(c->alpha[n]))
       return fail(PASD_ERR_INVALID_ARG, "lambda and alpha must be finite");
   }
@@ -121,7 +124,7 @@ int validate_impl(const pasd_config* c) {
 // Buffer plan shared by pasd_footprint and pasd_create.
 struct Plan {
   Layout L;
-  size_t off_T, off_D, off_sc, off_hist, off_prob;
+  size_t off_T, off_D, off_sc, off_hist, off_prob, off_views;
   size_t off_Y[kMaxN], off_P[kMaxN], off_U[kMaxN], off_Us[kMaxN], off_Uf[kMaxN], off_UfT[kMaxN],
       off_Mpart[kMaxN], off_M[kMaxN], off_Spart[kMaxN], off_Wf[kMaxN], off_Wev[kMaxN],
       off_Fac[kMaxN];
@@ -145,6 +148,7 @@ void make_plan(const pasd_config* c, Plan& p) {
     g.I = (int)c->dims[n];
     g.J = g.A * g.B;
     g.R = (int)c->ranks[n];
+    g.T = (g.R + kRT - 1) / kRT;
     p.mblocks[n] = gemm_m_blocks(g, N);
     p.sblocks[n] = gram_blocks(g);
   }
@@ -152,21 +156,23 @@ void make_plan(const pasd_config* c, Plan& p) {
   p.off_D = p.L.add(numel * es);
   p.off_sc = p.L.add(sizeof(DevScalars));
   p.off_prob = p.L.add(std::max(sizeof(Problem<float>), sizeof(Problem<double>)));
+  p.off_views = p.L.add(kMaxTiles * std::max(sizeof(Problem<float>), sizeof(Problem<double>)));
   p.off_hist = p.L.add(sizeof(double) * (size_t)c->max_iter * N);
   for (int n = 0; n < N; ++n) {
     const ModeGeom& g = p.geom[n];
+    const size_t RT = (size_t)g.T * kRT;
     p.off_Y[n] = p.L.add(numel * es);
-    p.off_P[n] = p.L.add((size_t)kRT * g.J * es);  // rows >= R stay zero
+    p.off_P[n] = p.L.add(RT * g.J * es);  // rows >= R stay zero
     p.off_U[n] = p.L.add((size_t)g.I * g.R * 8);
-    p.off_Us[n] = p.L.add((size_t)g.I * kRT * es);
-    p.off_Uf[n] = p.L.add((size_t)g.I * kRT * es);
-    p.off_UfT[n] = p.L.add((size_t)g.I * kRT * es);
-    p.off_Mpart[n] = p.L.add((size_t)p.mblocks[n] * g.I * kRT * 8);
-    p.off_M[n] = p.L.add((size_t)g.I * kRT * 8);
-    p.off_Spart[n] = p.L.add((size_t)p.sblocks[n] * kRT * kRT * 8);
-    p.off_Wf[n] = p.L.add(kRT * kRT * 8);
-    p.off_Wev[n] = p.L.add(kRT * kRT * 8);
-    p.off_Fac[n] = p.L.add(kRT * 8);
+    p.off_Us[n] = p.L.add((size_t)g.I * RT * es);
+    p.off_Uf[n] = p.L.add((size_t)g.I * RT * es);
+    p.off_UfT[n] = p.L.add((size_t)g.I * RT * es);
+    p.off_Mpart[n] = p.L.add((size_t)p.mblocks[n] * g.I * RT * 8);
+    p.off_M[n] = p.L.add((size_t)g.I * RT * 8);
+    p.off_Spart[n] = p.L.add((size_t)p.sblocks[n] * RT * RT * 8);
+    p.off_Wf[n] = p.L.add(RT * RT * 8);
+    p.off_Wev[n] = p.L.add(RT * RT * 8);
+    p.off_Fac[n] = p.L.add(RT * 8);
   }
 }
 
@@ -222,7 +228,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   // 32-bit offsets in the fused pass when every element offset, and every
   // index divided there, stays below 2^31 bytes
   int64_t span = p.numel;
-  for (int n = 0; n < ctx->N; ++n) span = std::max<int64_t>(span, (int64_t)kRT * p.g[n].J);
+  for (int n = 0; n < ctx->N; ++n) span = std::max<int64_t>(span, (int64_t)kRT * p.g[n].T * p.g[n].J);
   p.idx32 = span * (int64_t)sizeof(S) < (int64_t(1) << 31) ? 1 : 0;
   const int64_t IN = p.g[ctx->N - 1].I;
   p.fd_q = make_fastdiv((uint32_t)(p.idx32 ? IN / (p.vecw ? vw : 1) : 1));
@@ -232,6 +238,65 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     p.fd_i[n] = make_fastdiv((uint32_t)(inner ? p.g[n].I : 1));
     p.fd_b[n] = make_fastdiv((uint32_t)(n < ctx->N && p.g[n].B < (int64_t(1) << 31) ? p.g[n].B : 1));
   }
+}
+
+// Rank-tile views of a problem with some R_n > kRT (see Problem::wide): view t
+// keeps, for every mode with R_n > kRT t, tile t of the rank-indexed buffers
+// the unfolding GEMMs and the GEMM-M reduction touch, with R_n replaced by the
+// tile's R_t <= kRT; the other modes get no blocks.  Device copies follow the
+// problem's own in the allocation.
+template <typename S>
+void fill_views(pasd_ctx* ctx, const Plan& pl, Problem<S>& p, Problem<S>* views) {
+  int T = 1;
+  for (int n = 0; n < p.N; ++n) T = std::max(T, p.g[n].T);
+  p.wide = T > 1 ? 1 : 0;
+  p.ntiles = T;
+  for (int t = 0; t < kMaxTiles; ++t) {
+    p.view_host[t] = nullptr;
+    p.view_dev[t] = nullptr;
+  }
+  if (!p.wide) return;
+  char* dv = static_cast<char*>(ctx->base) + pl.off_views;
+  for (int t = 0; t < T; ++t) {
+    Problem<S>& v = views[t];
+    v = p;
+    v.wide = 0;
+    v.ntiles = 1;
+    for (int u = 0; u < kMaxTiles; ++u) {
+      v.view_host[u] = nullptr;
+      v.view_dev[u] = nullptr;
+    }
+    for (int k = 0; k < KB_COUNT; ++k) v.kb[k][0] = 0;
+    for (int n = 0; n < p.N; ++n) {
+      ModeGeom& g = v.g[n];
+      ModeBufs<S>& m = v.m[n];
+      const int Rt = std::min(kRT, p.g[n].R - kRT * t);
+      const bool has = Rt > 0;
+      if (has) {
+        g.R = Rt;
+        g.T = 1;
+        m.P += (int64_t)kRT * t * g.J;
+        m.Us += (int64_t)t * g.I * kRT;
+        m.Mpart += (int64_t)t * m.mblocks * g.I * kRT;
+        m.M += (int64_t)t * g.I * kRT;
+      }
+      v.kb[KB_GEMM_M][n + 1] = v.kb[KB_GEMM_M][n] + (has ? m.mblocks : 0);
+      v.kb[KB_REDUCE_M][n + 1] = v.kb[KB_REDUCE_M][n] + (has ? reduce_m_blocks(g) : 0);
+      v.kb[KB_GEMM_P][n + 1] = v.kb[KB_GEMM_P][n] + (has ? gemm_p_blocks(g) : 0);
+      v.kb[KB_GRAM][n + 1] = v.kb[KB_GRAM][n];
+    }
+    p.view_host[t] = &v;
+    p.view_dev[t] = reinterpret_cast<const Problem<S>*>(dv + (size_t)t * sizeof(Problem<S>));
+  }
+}
+
+template <typename S>
+hipError_t upload_problem(pasd_ctx* ctx, const Problem<S>& p) {
+  hipError_t e = hipMemcpyAsync(ctx->dev_prob, &p, sizeof(p), hipMemcpyHostToDevice, ctx->stream);
+  for (int t = 0; e == hipSuccess && p.wide && t < p.ntiles; ++t)
+    e = hipMemcpyAsync(const_cast<Problem<S>*>(p.view_dev[t]), p.view_host[t], sizeof(p),
+                       hipMemcpyHostToDevice, ctx->stream);
+  return e;
 }
 
 // Enqueue `count` iterations; with `ev` non-null an event is recorded before
@@ -449,10 +514,12 @@ int pasd_create(const pasd_config* cfg, const void* T, int T_on_device, pasd_ctx
   ctx->dev_prob = static_cast<char*>(ctx->base) + pl.off_prob;
   if (cfg->precision == PASD_FP64) {
     fill_problem<double>(ctx, pl, ctx->pd);
-    e = hipMemcpyAsync(ctx->dev_prob, &ctx->pd, sizeof(ctx->pd), hipMemcpyHostToDevice, ctx->stream);
+    fill_views<double>(ctx, pl, ctx->pd, ctx->vd);
+    e = upload_problem<double>(ctx, ctx->pd);
   } else {
     fill_problem<float>(ctx, pl, ctx->pf);
-    e = hipMemcpyAsync(ctx->dev_prob, &ctx->pf, sizeof(ctx->pf), hipMemcpyHostToDevice, ctx->stream);
+    fill_views<float>(ctx, pl, ctx->pf, ctx->vf);
+    e = upload_problem<float>(ctx, ctx->pf);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
@@ -600,39 +667,42 @@ int pasd_export(pasd_ctx* ctx, int q, int index, void* dst, int on_device) {
       bytes = (size_t)ctx->geom[index].R * ctx->geom[index].J * es;
       break;
     case PASD_Q_UF: {
-      // I x kRT padded state-type copy -> I x R double
+      // [T][I][kRT] padded state-type copy -> I x R double
       const ModeGeom& g = ctx->geom[index];
-      std::vector<char> tmp((size_t)g.I * kRT * es);
+      std::vector<char> tmp((size_t)g.I * kRT * g.T * es);
       const void* s = f64 ? (const void*)ctx->pd.m[index].Uf : (const void*)ctx->pf.m[index].Uf;
       HIP_TRY(hipMemcpyAsync(tmp.data(), s, tmp.size(), hipMemcpyDeviceToHost, ctx->stream));
       HIP_TRY(hipStreamSynchronize(ctx->stream));
       std::vector<double> outv((size_t)g.I * g.R);
       for (int i = 0; i < g.I; ++i)
-        for (int r = 0; r < g.R; ++r)
-          outv[(size_t)i * g.R + r] = f64 ? ((const double*)tmp.data())[(size_t)i * kRT + r]
-                                          : (double)((const float*)tmp.data())[(size_t)i * kRT + r];
+        for (int r = 0; r < g.R; ++r) {
+          const size_t at = ((size_t)(r / kRT) * g.I + i) * kRT + r % kRT;
+          outv[(size_t)i * g.R + r] = f64 ? ((const double*)tmp.data())[at]
+                                          : (double)((const float*)tmp.data())[at];
+        }
       HIP_TRY(hipMemcpy(dst, outv.data(), outv.size() * 8,
                         on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
       return PASD_OK;
     }
     case PASD_Q_WEV: {
-      const int R = ctx->geom[index].R;
-      double w[kRT * kRT], out[kRT * kRT];
+      const int R = ctx->geom[index].R, RT = ctx->geom[index].T * kRT;
+      std::vector<double> w((size_t)RT * RT), out((size_t)R * R);
       const double* s = f64 ? ctx->pd.m[index].Wev : ctx->pf.m[index].Wev;
-      HIP_TRY(hipMemcpyAsync(w, s, sizeof(w), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(hipMemcpyAsync(w.data(), s, w.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
       HIP_TRY(hipStreamSynchronize(ctx->stream));
       for (int r = 0; r < R; ++r)
-        for (int c = 0; c < R; ++c) out[r * R + c] = w[r * kRT + c];
-      HIP_TRY(hipMemcpy(dst, out, sizeof(double) * R * R,
+        for (int c = 0; c < R; ++c) out[(size_t)r * R + c] = w[(size_t)r * RT + c];
+      HIP_TRY(hipMemcpy(dst, out.data(), out.size() * 8,
                         on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
       return PASD_OK;
     }
     case PASD_Q_FAC: {
-      double f[kRT];
+      const int R = ctx->geom[index].R;
+      std::vector<double> f(R);
       const double* s = f64 ? ctx->pd.m[index].Fac : ctx->pf.m[index].Fac;
-      HIP_TRY(hipMemcpyAsync(f, s, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+      HIP_TRY(hipMemcpyAsync(f.data(), s, f.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
       HIP_TRY(hipStreamSynchronize(ctx->stream));
-      HIP_TRY(hipMemcpy(dst, f, sizeof(double) * ctx->geom[index].R,
+      HIP_TRY(hipMemcpy(dst, f.data(), f.size() * 8,
                         on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
       return PASD_OK;
     }
@@ -695,13 +765,14 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
       HIP_TRY(hipMemcpy(u.data(), src, u.size() * 8, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
       void* d = f64 ? (void*)ctx->pd.m[index].U : (void*)ctx->pf.m[index].U;
       HIP_TRY(hipMemcpy(d, u.data(), u.size() * 8, hipMemcpyHostToDevice));
-      std::vector<char> us((size_t)g.I * kRT * es, 0);
+      std::vector<char> us((size_t)g.I * kRT * g.T * es, 0);
       for (int i = 0; i < g.I; ++i)
         for (int r = 0; r < g.R; ++r) {
+          const size_t at = ((size_t)(r / kRT) * g.I + i) * kRT + r % kRT;
           if (f64)
-            ((double*)us.data())[(size_t)i * kRT + r] = u[(size_t)i * g.R + r];
+            ((double*)us.data())[at] = u[(size_t)i * g.R + r];
           else
-            ((float*)us.data())[(size_t)i * kRT + r] = (float)u[(size_t)i * g.R + r];
+            ((float*)us.data())[at] = (float)u[(size_t)i * g.R + r];
         }
       void* ds = f64 ? (void*)ctx->pd.m[index].Us : (void*)ctx->pf.m[index].Us;
       HIP_TRY(hipMemcpy(ds, us.data(), us.size(), hipMemcpyHostToDevice));
@@ -713,24 +784,24 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
       return PASD_OK;
     }
     case PASD_Q_WEV: {
-      const int R = ctx->geom[index].R;
-      double in[kRT * kRT], w[kRT * kRT];
-      HIP_TRY(hipMemcpy(in, src, sizeof(double) * R * R,
+      const int R = ctx->geom[index].R, RT = ctx->geom[index].T * kRT;
+      std::vector<double> in((size_t)R * R), w((size_t)RT * RT);
+      HIP_TRY(hipMemcpy(in.data(), src, in.size() * 8,
                         on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
-      for (int r = 0; r < kRT; ++r)
-        for (int c = 0; c < kRT; ++c)
-          w[r * kRT + c] = (r < R && c < R) ? in[r * R + c] : (r == c ? 1.0 : 0.0);
+      for (int r = 0; r < RT; ++r)
+        for (int c = 0; c < RT; ++c)
+          w[(size_t)r * RT + c] = (r < R && c < R) ? in[(size_t)r * R + c] : (r == c ? 1.0 : 0.0);
       double* d = f64 ? ctx->pd.m[index].Wev : ctx->pf.m[index].Wev;
-      HIP_TRY(hipMemcpy(d, w, sizeof(w), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(d, w.data(), w.size() * 8, hipMemcpyHostToDevice));
       return PASD_OK;
     }
     case PASD_Q_FAC: {
       const int R = ctx->geom[index].R;
-      double f[kRT] = {0};
-      HIP_TRY(hipMemcpy(f, src, sizeof(double) * R,
+      std::vector<double> f((size_t)ctx->geom[index].T * kRT, 0.0);
+      HIP_TRY(hipMemcpy(f.data(), src, sizeof(double) * R,
                         on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
       double* d = f64 ? ctx->pd.m[index].Fac : ctx->pf.m[index].Fac;
-      HIP_TRY(hipMemcpy(d, f, sizeof(f), hipMemcpyHostToDevice));
+      HIP_TRY(hipMemcpy(d, f.data(), f.size() * 8, hipMemcpyHostToDevice));
       return PASD_OK;
     }
     case PASD_Q_SCALARS: {

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpasd.so")
 
 MAX_ORDER = 8
-MAX_RANK = 16
+MAX_RANK = 64
 
 OK = 0
 NOT_CONVERGED = 1
