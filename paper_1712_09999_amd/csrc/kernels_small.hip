@@ -922,24 +922,75 @@ __global__ void __launch_bounds__(256) k_tiebreak(Batch<S> bt) {
 // ---------------------------------------------------------------------------
 constexpr int kQrLdsW = 16384;  // doubles of LDS for M when R_n > kRT (I_n * R_n <= 16384)
 constexpr int kMR = PASD_MAX_RANK;
+// The rank-wide QR and eigensolver are latency bound (sequential column steps
+// and Jacobi rounds): 512 threads, two waves per SIMD, hide part of it.
+constexpr int kWideThreads = 512;
+constexpr int kWideWaves = kWideThreads / 64;
 
-// Sum over the 256 threads of a block in a fixed order (red: 4 doubles of LDS).
-__device__ __forceinline__ double block_sum256(double v, double* red) {
+// Sum over the threads of a kWideThreads block in a fixed order (red: one
+// double of LDS per wave).
+__device__ __forceinline__ double block_sum_wide(double v, double* red) {
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWideWaves; ++w) s += red[w];
   __syncthreads();
   return s;
 }
 
-// Householder QR of M_n (I x R, column-major in LDS) by a 256-thread block, the
-// same reflectors as k_qr (LAPACK dgeqr2 / dorg2r conventions): wave w applies
-// the reflector of a column step to columns c + 1 + w, c + 5, ..., each one a
-// wave-wide dot product followed by its update, so the waves need no barrier
-// between the two.
+// Applies the reflector of column c (v = (1, A[c+1:, c]), tau t) to the
+// columns j = c + 1 + wave + kWideWaves u < R that this wave owns: d_j = v^T A[c:, j],
+// then A[c:, j] -= t d_j v.  The dot products of all of the wave's columns
+// are accumulated and reduced together, without branches (a column index past
+// R reads column c and its result is dropped), so a column step costs one
+// chain of LDS and shuffle latencies rather than one per column; only the
+// stores are conditional.  `wave` must be uniform (readfirstlane).
+__device__ __forceinline__ void qrw_reflect(double* A, int I, int R, int c, double t, int lane,
+                                            int wave) {
+  constexpr int NU = kMR / kWideWaves;
+  int col[NU];
+  bool ok[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int j = c + 1 + wave + kWideWaves * u;
+    ok[u] = j < R;
+    col[u] = (ok[u] ? j : c) * I;
+  }
+  double d[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) d[u] = 0.0;
+  for (int i = c + 1 + lane; i < I; i += 64) {
+    const double v = A[c * I + i];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) d[u] = fma(v, A[col[u] + i], d[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) d[u] = wave_sum(d[u]);
+#pragma unroll
+  for (int u = 0; u < NU; ++u) d[u] = ok[u] ? d[u] + A[col[u] + c] : 0.0;
+  if (t == 0.0) return;
+  for (int i = c + 1 + lane; i < I; i += 64) {
+    const double v = A[c * I + i];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (ok[u]) A[col[u] + i] -= t * d[u] * v;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+      if (ok[u]) A[col[u] + c] -= t * d[u];
+  }
+}
+
+// Householder QR of M_n (I x R, column-major in LDS) by one block, the same
+// reflectors as k_qr (LAPACK dgeqr2 / dorg2r conventions): wave w applies the
+// reflector of a column step to columns c + 1 + w, c + 1 + w + kWideWaves, ...
+// (qrw_reflect), each a wave-wide dot product followed by its update, so the
+// waves need no barrier between the two.
 template <typename S>
-__global__ void __launch_bounds__(256) k_qr_w(Batch<S> bt) {
+__global__ void __launch_bounds__(kWideThreads) k_qr_w(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
   const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done || pb.sc->k == 0) return;
@@ -947,22 +998,22 @@ __global__ void __launch_bounds__(256) k_qr_w(Batch<S> bt) {
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int I = g.I, R = g.R, T = g.T, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   __shared__ double A[kQrLdsW];  // column-major A[c * I + i]
   __shared__ double tau[kMR];
-  __shared__ double red[4];
-  for (int e = tid; e < I * R; e += 256) {
+  __shared__ double red[kWideWaves];
+  for (int e = tid; e < I * R; e += kWideThreads) {
     const int c = e / I, i = e - c * I;
     A[e] = mb.M[((int64_t)(c / kRT) * I + i) * kRT + c % kRT];
   }
   __syncthreads();
   for (int c = 0; c < R; ++c) {
     double part = 0;
-    for (int i = c + 1 + tid; i < I; i += 256) {
+    for (int i = c + 1 + tid; i < I; i += kWideThreads) {
       const double x = A[c * I + i];
       part += x * x;
     }
-    const double xnorm2 = block_sum256(part, red);
+    const double xnorm2 = block_sum_wide(part, red);
     const double alpha = A[c * I + c];
     double t = 0, beta = alpha, scale = 0;
     if (xnorm2 > 0) {
@@ -971,17 +1022,9 @@ __global__ void __launch_bounds__(256) k_qr_w(Batch<S> bt) {
       scale = 1.0 / (alpha - beta);
     }
     if (xnorm2 > 0)
-      for (int i = c + 1 + tid; i < I; i += 256) A[c * I + i] *= scale;
+      for (int i = c + 1 + tid; i < I; i += kWideThreads) A[c * I + i] *= scale;
     __syncthreads();
-    for (int j = c + 1 + wave; j < R; j += 4) {
-      double d = 0;
-      for (int i = c + 1 + lane; i < I; i += 64) d += A[c * I + i] * A[j * I + i];
-      d = wave_sum(d) + A[j * I + c];
-      if (t != 0) {
-        for (int i = c + 1 + lane; i < I; i += 64) A[j * I + i] -= t * d * A[c * I + i];
-        if (lane == 0) A[j * I + c] -= t * d;
-      }
-    }
+    qrw_reflect(A, I, R, c, t, lane, wave);
     if (tid == 0) {
       A[c * I + c] = beta;
       tau[c] = t;
@@ -990,20 +1033,14 @@ __global__ void __launch_bounds__(256) k_qr_w(Batch<S> bt) {
   }
   for (int c = R - 1; c >= 0; --c) {
     const double t = tau[c];
-    for (int j = c + 1 + wave; j < R; j += 4) {
-      double d = 0;
-      for (int i = c + 1 + lane; i < I; i += 64) d += A[c * I + i] * A[j * I + i];
-      d = wave_sum(d) + A[j * I + c];
-      for (int i = c + 1 + lane; i < I; i += 64) A[j * I + i] -= t * d * A[c * I + i];
-      if (lane == 0) A[j * I + c] -= t * d;
-    }
+    qrw_reflect(A, I, R, c, t, lane, wave);
     __syncthreads();
-    for (int i = c + 1 + tid; i < I; i += 256) A[c * I + i] = -t * A[c * I + i];
+    for (int i = c + 1 + tid; i < I; i += kWideThreads) A[c * I + i] = -t * A[c * I + i];
     if (tid == 0) A[c * I + c] = 1.0 - t;
-    for (int i = tid; i < c; i += 256) A[c * I + i] = 0.0;
+    for (int i = tid; i < c; i += kWideThreads) A[c * I + i] = 0.0;
     __syncthreads();
   }
-  for (int e = tid; e < I * T * kRT; e += 256) {
+  for (int e = tid; e < I * T * kRT; e += kWideThreads) {
     const int t = e / (I * kRT), rem = e - t * I * kRT;
     const int i = rem / kRT, c = t * kRT + rem % kRT;
     const double v = c < R ? A[c * I + i] : 0.0;
@@ -1057,10 +1094,17 @@ __global__ void __launch_bounds__(256) k_tiebreak_w(Batch<S> bt) {
 // partials, the warm start S' = W0^T S W0, round-robin Jacobi sweeps until no
 // pair needs a rotation, then W_f = W diag(f) W^T and U W_f.  A round computes
 // the R'/2 rotations once (one thread per pair, into LDS), then every thread
-// applies them to its 2 x 2 blocks of the matrix (read from one buffer,
-// written to the other) and to its entries of the eigenvectors.
+// applies them to its 2 x 2 blocks (k, l), k <= l, of the matrix (read from
+// one buffer, written to the other) and to its entries of the eigenvectors.
+// Each thread has fixed slots (block tid + kWideThreads u, eigenvector entry
+// tid + kWideThreads u)
+// whose indices are clamped into range, so that all reads of a phase are
+// issued together; only the writes of valid slots happen.
+constexpr int kEigBlk = (kMR / 2) * (kMR / 2 + 1) / 2;  // blocks (k, l), k <= l
+constexpr int kEigBU = (kEigBlk + kWideThreads - 1) / kWideThreads;
+constexpr int kEigWU = (kMR * (kMR / 2) + kWideThreads - 1) / kWideThreads;
 template <typename S>
-__global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
+__global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
   const Problem<S>& pb = *bt.p[req];
   if (pb.sc->done) return;
@@ -1074,8 +1118,9 @@ __global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
   __shared__ double T1[kMR][kMR + 1];
   __shared__ double rot[kMR / 2][3];
   __shared__ double fac[kMR];
+  __shared__ int blk_kl[kEigBlk];  // (k << 8) | l of block slot e
   const int nb = mb.sblocks;
-  for (int e = tid; e < RT * RT; e += 256) {
+  for (int e = tid; e < RT * RT; e += kWideThreads) {
     const int r = e / RT, c = e - r * RT;
     const bool in = r < R && c < R;
     double sm = 0.0;
@@ -1085,14 +1130,14 @@ __global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
     W[r][c] = (warm && in) ? mb.Wev[e] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int e = tid; e < RT * RT; e += 256) {  // T1 = S W0, S from its upper triangle
+  for (int e = tid; e < RT * RT; e += kWideThreads) {  // T1 = S W0, S from its upper triangle
     const int r = e / RT, c = e - r * RT;
     double t = 0;
     for (int k = 0; k < R; ++k) t += (r <= k ? Sb[0][r][k] : Sb[0][k][r]) * W[k][c];
     T1[r][c] = t;
   }
   __syncthreads();
-  for (int e = tid; e < RT * RT; e += 256) {  // S' = W0^T T1, symmetric by construction
+  for (int e = tid; e < RT * RT; e += kWideThreads) {  // S' = W0^T T1, symmetric by construction
     const int r = e / RT, c = e - r * RT;
     const int rr = r <= c ? r : c, cc = r <= c ? c : r;
     double v = 0;
@@ -1104,11 +1149,26 @@ __global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
   const int Rp = R + (R & 1);
   const int half = Rp / 2;
   const int m = Rp - 1;
+  const int nblk = half * (half + 1) / 2;
+  const int nwe = R * half;
+  // i = e / half for e < kMR * kMR / 2 by multiply and shift: with
+  // mh = ceil(2^16 / half) the error of e mh / 2^16 is below 2048 / 2^16 = 1/32,
+  // and the fractional part of e / half is at most 1 - 1/half <= 1 - 1/32
+  const int mh = half > 0 ? (65536 + half - 1) / half : 0;
+  for (int e = tid; e < nblk; e += kWideThreads) {
+    int k = 0, rem = e;
+    while (rem >= half - k) {
+      rem -= half - k;
+      ++k;
+    }
+    blk_kl[e] = (k << 8) | (k + rem);
+  }
+  __syncthreads();
   int sweeps = 0;
   int cur = 1;
   for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
     int need = 0;
-    for (int e = tid; e < R * R; e += 256) {
+    for (int e = tid; e < R * R; e += kWideThreads) {
       const int p = e / R, q = e - p * R;
       if (p < q) need |= jacobi_needed(Sb[cur], p, q, thr) ? 1 : 0;
     }
@@ -1127,43 +1187,72 @@ __global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
         rot[tid][2] = t;
       }
       __syncthreads();
-      for (int e = tid; e < half * half; e += 256) {
-        const int k = e / half, l = e - k * half;
-        if (k > l) continue;
-        int pk, qk, pl, ql;
-        rr_pair(rd, k, m, pk, qk);
-        rr_pair(rd, l, m, pl, ql);
-        const double ck = rot[k][0], sk = rot[k][1], tk = rot[k][2];
-        const double cl = rot[l][0], sl = rot[l][1];
-        const double x00 = A[pk][pl], x01 = A[pk][ql], x10 = A[qk][pl], x11 = A[qk][ql];
-        const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
-        const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
-        double z00 = cl * y00 - sl * y01, z01 = sl * y00 + cl * y01;
-        double z10 = cl * y10 - sl * y11, z11 = sl * y10 + cl * y11;
-        if (k == l && sk != 0.0) {
-          const double tb = tk * x01;
-          z00 = x00 - tb;
-          z11 = x11 + tb;
-          z01 = 0.0;
-          z10 = 0.0;
+      {
+        int pk[kEigBU], qk[kEigBU], pl[kEigBU], ql[kEigBU];
+        bool diag[kEigBU];
+        double ck[kEigBU], sk[kEigBU], tk[kEigBU], cl[kEigBU], sl[kEigBU], x[kEigBU][4];
+#pragma unroll
+        for (int u = 0; u < kEigBU; ++u) {
+          const int e = min(tid + kWideThreads * u, nblk - 1);
+          const int kl = blk_kl[e];
+          const int k = kl >> 8, l = kl & 255;
+          diag[u] = k == l;
+          rr_pair(rd, k, m, pk[u], qk[u]);
+          rr_pair(rd, l, m, pl[u], ql[u]);
+          ck[u] = rot[k][0];
+          sk[u] = rot[k][1];
+          tk[u] = rot[k][2];
+          cl[u] = rot[l][0];
+          sl[u] = rot[l][1];
+          x[u][0] = A[pk[u]][pl[u]];
+          x[u][1] = A[pk[u]][ql[u]];
+          x[u][2] = A[qk[u]][pl[u]];
+          x[u][3] = A[qk[u]][ql[u]];
         }
-        B[pk][pl] = z00;
-        B[pk][ql] = z01;
-        B[qk][pl] = z10;
-        B[qk][ql] = z11;
-        B[pl][pk] = z00;
-        B[ql][pk] = z01;
-        B[pl][qk] = z10;
-        B[ql][qk] = z11;
-      }
-      for (int e = tid; e < R * half; e += 256) {
-        const int i = e / half, l = e - i * half;
-        int pl, ql;
-        rr_pair(rd, l, m, pl, ql);
-        const double cl = rot[l][0], sl = rot[l][1];
-        const double wp = W[i][pl], wq = W[i][ql];
-        W[i][pl] = cl * wp - sl * wq;
-        W[i][ql] = sl * wp + cl * wq;
+        int pw[kEigWU], qw[kEigWU], iw[kEigWU];
+        double cw[kEigWU], sw[kEigWU], wp[kEigWU], wq[kEigWU];
+#pragma unroll
+        for (int u = 0; u < kEigWU; ++u) {
+          const int e = min(tid + kWideThreads * u, nwe - 1);
+          const int i = (e * mh) >> 16, l = e - i * half;
+          iw[u] = i;
+          rr_pair(rd, l, m, pw[u], qw[u]);
+          cw[u] = rot[l][0];
+          sw[u] = rot[l][1];
+          wp[u] = W[i][pw[u]];
+          wq[u] = W[i][qw[u]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kEigBU; ++u) {
+          if (tid + kWideThreads * u >= nblk) continue;
+          const double x00 = x[u][0], x01 = x[u][1], x10 = x[u][2], x11 = x[u][3];
+          const double y00 = ck[u] * x00 - sk[u] * x10, y01 = ck[u] * x01 - sk[u] * x11;
+          const double y10 = sk[u] * x00 + ck[u] * x10, y11 = sk[u] * x01 + ck[u] * x11;
+          double z00 = cl[u] * y00 - sl[u] * y01, z01 = sl[u] * y00 + cl[u] * y01;
+          double z10 = cl[u] * y10 - sl[u] * y11, z11 = sl[u] * y10 + cl[u] * y11;
+          if (diag[u] && sk[u] != 0.0) {
+            const double tb = tk[u] * x01;
+            z00 = x00 - tb;
+            z11 = x11 + tb;
+            z01 = 0.0;
+            z10 = 0.0;
+          }
+          B[pk[u]][pl[u]] = z00;
+          B[pk[u]][ql[u]] = z01;
+          B[qk[u]][pl[u]] = z10;
+          B[qk[u]][ql[u]] = z11;
+          B[pl[u]][pk[u]] = z00;
+          B[ql[u]][pk[u]] = z01;
+          B[pl[u]][qk[u]] = z10;
+          B[ql[u]][qk[u]] = z11;
+        }
+#pragma unroll
+        for (int u = 0; u < kEigWU; ++u) {
+          if (tid + kWideThreads * u >= nwe) continue;
+          W[iw[u]][pw[u]] = cw[u] * wp[u] - sw[u] * wq[u];
+          W[iw[u]][qw[u]] = sw[u] * wp[u] + cw[u] * wq[u];
+        }
       }
       __syncthreads();
       cur ^= 1;
@@ -1186,7 +1275,7 @@ __global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
     const int cnt = __popcll(__ballot(tid < R && fac[tid] > 0.0));
     if (tid == 0) pb.sc->rank[n] = cnt;
   }
-  for (int e = tid; e < RT * RT; e += 256) {
+  for (int e = tid; e < RT * RT; e += kWideThreads) {
     const int r = e / RT, c = e - r * RT;
     double sm = 0.0;
     if (r < R && c < R)
@@ -1196,10 +1285,10 @@ __global__ void __launch_bounds__(256) k_eig_w(Batch<S> bt) {
     mb.Wev[e] = (r < R && c < R) ? W[r][c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  // U W_f: lane c is a column of the result, wave w takes rows w, w + 4, ...
+  // U W_f: lane c is a column of the result, wave w takes rows w, w + kWideWaves, ...
   const int c = tid & 63;
   if (c < RT) {
-    for (int i = tid >> 6; i < I; i += 4) {
+    for (int i = tid >> 6; i < I; i += kWideWaves) {
       const double* urow = mb.U + (int64_t)i * R;
       double acc = 0.0;
 #pragma unroll 8
@@ -1262,7 +1351,7 @@ void launch_qr(const LaunchSet<S>& ls, hipStream_t s) {
     bool keep = false;
     for (int r = 0; r < wid.count; ++r) keep = keep || wid.host[r]->tiebreak_keep;
     if (keep) hipLaunchKernelGGL(k_tiebreak_w<S>, dim3(grid), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(k_qr_w<S>, dim3(grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_qr_w<S>, dim3(grid), dim3(kWideThreads), 0, s, b);
   }
 }
 
@@ -1277,7 +1366,7 @@ void launch_eig(const LaunchSet<S>& ls, hipStream_t s) {
   }
   if (wid.count) {
     const int grid = make_batch(wid, b, [](const Problem<S>& p) { return p.N; });
-    hipLaunchKernelGGL(k_eig_w<S>, dim3(grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_eig_w<S>, dim3(grid), dim3(kWideThreads), 0, s, b);
   }
 }
 
