@@ -11,7 +11,8 @@
 // Y_n (definition under eq. (9)); G is never stored.
 //
 // All three use v_mfma_{f32,f64}_16x16x4 with the rank padded to one 16-wide
-// tile.  The unfolding is read in place through its (A, I, B) geometry.  The
+// tile (ranks above 16 run as several one-tile problems, see for_tile_sets,
+// and the Gram has a rank-wide variant, k_gram_w).  The unfolding is read in place through its (A, I, B) geometry.  The
 // contraction index inside one MFMA is permuted freely (both operands use the
 // same permutation), which lets every lane issue 4-element vector loads along
 // the contiguous direction of the tensor.  Split-K partial sums are reduced
