@@ -194,6 +194,75 @@ def phase_bench(rs, rhos, trials, dim=100, seed0=17125000):
             "solves_per_s": round(len(res) / wall, 2), "iters_per_s": round(iters / wall, 1)}
 
 
+def wide_rank_bench(rs, precision="fp64", iters=40):
+    """Per-kernel times of one 100^3 solve at Tucker rank r with R_n =
+    floor(1.2 r) (the Fig. 1 workload), from HIP events between launches over
+    `iters` iterations after 30 warm-up iterations, and the graph-replay
+    iteration time; R_n > 16 runs the rank-tiled path."""
+    import torch
+
+    from workloads.torch_gen import tucker_on_device
+    from paper_1712_09999_amd import pasd as P
+
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    rows = []
+    for r in rs:
+        R = int(1.2 * r)
+        T, _, _ = tucker_on_device((100, 100, 100), (r, r, r), 0.1, 17126000 + r,
+                                   value_range=(-1.0, 1.0), dtype=dt, scale=None)
+        s = P.Solver(T, (R, R, R), precision=precision, tol=0.0, max_iter=100000, device=0)
+        s.step(30)
+        prof = s.profile(iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(64)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / 64 * 1e3
+        info = s.query()
+        rows.append({"r": r, "R": R, "ms_per_iter": round(ms, 4),
+                     "eig_sweeps": list(info.eig_sweeps[:3]),
+                     "kernels_us": {k: round(v[0] / max(v[1], 1) * 1e3, 1) for k, v in prof.items()}})
+        s.close()
+        _progress(f"wide rank r={r} R={R}: {ms:.3f} ms/iter")
+    return {"dims": [100, 100, 100], "precision": precision, "rows": rows}
+
+
+def mri_bench(rhos):
+    """The MRI-shaped stand-in of Section 5.2 (181 x 217 x 181, R_n = 40, a
+    fraction rho of the voxels replaced by U(0, 255); the MRI data itself is not
+    available, see workloads.mri_standin): one FP32 and one FP64 solve per rho
+    with the input resident on the GPU, iterations, solve time and PSNR."""
+    import torch
+
+    import workloads
+    from paper_1712_09999_amd import pasd as P
+
+    rows = []
+    for rho in rhos:
+        wl = workloads.mri_standin(rho)
+        row = {"rho": rho, "psnr_observed_db": round(workloads.psnr(wl.T, wl.L), 2)}
+        for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+            Td = torch.from_numpy(wl.T).to(device="cuda", dtype=dt).contiguous()
+            s = P.Solver(Td, wl.ranks, precision=prec, tol=wl.tol, max_iter=wl.max_iter, device=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.solve()
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+            X = s.result()[0].double().cpu().numpy()
+            row[prec] = {"iterations": info.iterations, "converged": bool(info.converged),
+                         "solve_ms": round(dt_s * 1e3, 1),
+                         "ms_per_iter": round(dt_s * 1e3 / max(info.iterations, 1), 3),
+                         "psnr_db": round(workloads.psnr(X, wl.L), 2)}
+            s.close()
+        rows.append(row)
+        _progress(f"mri stand-in rho={rho}: fp32 {row['fp32']['solve_ms']} ms "
+                  f"({row['fp32']['iterations']} it), fp64 {row['fp64']['solve_ms']} ms, "
+                  f"PSNR {row['psnr_observed_db']} -> {row['fp64']['psnr_db']} dB")
+    return {"dims": [181, 217, 181], "ranks": [40, 40, 40], "data": "synthetic stand-in",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +279,8 @@ def main():
                     help="the full Fig. 1 grid (r = 2..50 and rho = 2..50%% in steps of 2, "
                          "--phase-trials each) instead of every fourth point")
     ap.add_argument("--phase-trials", type=int, default=1)
+    ap.add_argument("--no-mri", action="store_true")
+    ap.add_argument("--no-wide", action="store_true")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (3 times), the "
                          "reference kernel that scales hardware traffic counters to bytes")
@@ -341,6 +412,12 @@ def main():
         rs = list(range(2, 51, 2))[::step]
         rhos = [round(0.02 * k, 2) for k in range(1, 26)][::step]
         out["phase_transition"] = phase_bench(rs, rhos, args.phase_trials)
+
+    if not args.no_wide:
+        out["wide_rank"] = wide_rank_bench([10, 30, 50])
+
+    if not args.no_mri:
+        out["mri_standin"] = mri_bench([0.05, 0.10, 0.20, 0.30])
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(T64, ranks, args.cpu_iters)

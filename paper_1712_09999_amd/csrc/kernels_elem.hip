@@ -417,15 +417,18 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
   // Stopping test of Algorithm 1 (line 8).  In FP32 state the N copies Z_n are
   // each rebuilt from FP32 factors, so they disagree by a few units in the last
   // place of |D|, and the residual T - Z_n - E cannot be certified below that:
-  // the test uses max(tol, 8 u max|D|), u the unit roundoff of the state type
-  // (2^-24 for FP32; 2^-53 leaves the FP64 test unchanged in practice).  With
-  // BF16 GEMM inputs P_n carries the rounding of its operands, and u is the
-  // measured relative level of the disagreement that leaves.
-  const double u = pb.precision == PASD_BF16_GEMM ? kBf16Level
-                   : sizeof(S) == 4               ? 5.9604644775390625e-08
-                                                  : 1.1102230246251565e-16;
+  // the test uses max(tol, c u max|D|), u the unit roundoff of the state type
+  // (2^-53 leaves the FP64 test unchanged in practice).  For the FP32 state
+  // c u = 16 * 2^-24: Z_n sums R_n rank terms rounded in FP32, and where the
+  // data's magnitude makes the allowance bind (values up to 255) the residual
+  // levels off at 8-12 u max|D| (measured at R_n = 16 and 40).  With BF16 GEMM
+  // inputs P_n carries the rounding of its operands, u is the measured relative
+  // level of the disagreement that leaves, and c = 8.
+  const double cu = pb.precision == PASD_BF16_GEMM ? 8.0 * kBf16Level
+                    : sizeof(S) == 4               ? 9.5367431640625e-07
+                                                   : 8.0 * 1.1102230246251565e-16;
   const double dmax = res[pb.N];
-  const double tol_eff = pb.tol > 0.0 ? fmax(pb.tol, 8.0 * u * dmax) : 0.0;  // tol 0: never stop
+  const double tol_eff = pb.tol > 0.0 ? fmax(pb.tol, cu * dmax) : 0.0;  // tol 0: never stop
   sc->dmax = dmax;
   sc->tol_eff = tol_eff;
   bool conv = true, bad = false;

@@ -940,15 +940,15 @@ __device__ __forceinline__ double block_sum_wide(double v, double* red) {
   return s;
 }
 
-// Applies the reflector of column c (v = (1, A[c+1:, c]), tau t) to the
+// Applies the reflector of column c (v = (1, scale A[c+1:, c]), tau t) to the
 // columns j = c + 1 + wave + kWideWaves u < R that this wave owns: d_j = v^T A[c:, j],
 // then A[c:, j] -= t d_j v.  The dot products of all of the wave's columns
 // are accumulated and reduced together, without branches (a column index past
 // R reads column c and its result is dropped), so a column step costs one
 // chain of LDS and shuffle latencies rather than one per column; only the
 // stores are conditional.  `wave` must be uniform (readfirstlane).
-__device__ __forceinline__ void qrw_reflect(double* A, int I, int R, int c, double t, int lane,
-                                            int wave) {
+__device__ __forceinline__ void qrw_reflect(double* A, int I, int R, int c, double t,
+                                            double scale, int lane, int wave) {
   constexpr int NU = kMR / kWideWaves;
   int col[NU];
   bool ok[NU];
@@ -969,13 +969,13 @@ __device__ __forceinline__ void qrw_reflect(double* A, int I, int R, int c, doub
 #pragma unroll
   for (int u = 0; u < NU; ++u) d[u] = wave_sum(d[u]);
 #pragma unroll
-  for (int u = 0; u < NU; ++u) d[u] = ok[u] ? d[u] + A[col[u] + c] : 0.0;
+  for (int u = 0; u < NU; ++u) d[u] = ok[u] ? fma(scale, d[u], A[col[u] + c]) : 0.0;
   if (t == 0.0) return;
   for (int i = c + 1 + lane; i < I; i += 64) {
     const double v = A[c * I + i];
 #pragma unroll
     for (int u = 0; u < NU; ++u)
-      if (ok[u]) A[col[u] + i] -= t * d[u] * v;
+      if (ok[u]) A[col[u] + i] -= t * d[u] * scale * v;
   }
   if (lane == 0) {
 #pragma unroll
@@ -988,7 +988,12 @@ __device__ __forceinline__ void qrw_reflect(double* A, int I, int R, int c, doub
 // reflectors as k_qr (LAPACK dgeqr2 / dorg2r conventions): wave w applies the
 // reflector of a column step to columns c + 1 + w, c + 1 + w + kWideWaves, ...
 // (qrw_reflect), each a wave-wide dot product followed by its update, so the
-// waves need no barrier between the two.
+// waves need no barrier between the two.  A factorisation step has one
+// barrier: the reflector's scale is applied on the fly (the stored column is
+// scaled, and its diagonal and tau written, during the next step, which does
+// not read it), and wave 0, which owns column c + 1, forms that column's norm
+// right after updating it (double-buffered, as the other waves may still be
+// reading the previous one).
 template <typename S>
 __global__ void __launch_bounds__(kWideThreads) k_qr_w(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
@@ -1002,18 +1007,33 @@ __global__ void __launch_bounds__(kWideThreads) k_qr_w(Batch<S> bt) {
   __shared__ double A[kQrLdsW];  // column-major A[c * I + i]
   __shared__ double tau[kMR];
   __shared__ double red[kWideWaves];
+  __shared__ double nrm[2];  // squared norm below the diagonal of the next column
   for (int e = tid; e < I * R; e += kWideThreads) {
     const int c = e / I, i = e - c * I;
     A[e] = mb.M[((int64_t)(c / kRT) * I + i) * kRT + c % kRT];
   }
   __syncthreads();
-  for (int c = 0; c < R; ++c) {
+  {
     double part = 0;
-    for (int i = c + 1 + tid; i < I; i += kWideThreads) {
-      const double x = A[c * I + i];
+    for (int i = 1 + tid; i < I; i += kWideThreads) {
+      const double x = A[i];
       part += x * x;
     }
-    const double xnorm2 = block_sum_wide(part, red);
+    part = block_sum_wide(part, red);
+    if (tid == 0) nrm[0] = part;
+    __syncthreads();
+  }
+  double pscale = 1.0, pbeta = 0.0, pt = 0.0;  // step c - 1, applied during step c
+  for (int c = 0; c < R; ++c) {
+    if (c > 0) {
+      if (pscale != 1.0)
+        for (int i = c + tid; i < I; i += kWideThreads) A[(c - 1) * I + i] *= pscale;
+      if (tid == 0) {
+        A[(c - 1) * I + c - 1] = pbeta;
+        tau[c - 1] = pt;
+      }
+    }
+    const double xnorm2 = nrm[c & 1];
     const double alpha = A[c * I + c];
     double t = 0, beta = alpha, scale = 0;
     if (xnorm2 > 0) {
@@ -1021,19 +1041,31 @@ __global__ void __launch_bounds__(kWideThreads) k_qr_w(Batch<S> bt) {
       t = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    if (xnorm2 > 0)
-      for (int i = c + 1 + tid; i < I; i += kWideThreads) A[c * I + i] *= scale;
-    __syncthreads();
-    qrw_reflect(A, I, R, c, t, lane, wave);
-    if (tid == 0) {
-      A[c * I + c] = beta;
-      tau[c] = t;
+    qrw_reflect(A, I, R, c, t, scale, lane, wave);
+    if (wave == 0 && c + 1 < R) {
+      double part = 0;
+      for (int i = c + 2 + lane; i < I; i += 64) {
+        const double x = A[(c + 1) * I + i];
+        part += x * x;
+      }
+      part = wave_sum(part);
+      if (lane == 0) nrm[(c + 1) & 1] = part;
     }
+    pscale = xnorm2 > 0 ? scale : 1.0;
+    pbeta = beta;
+    pt = t;
     __syncthreads();
   }
+  if (pscale != 1.0)
+    for (int i = R + tid; i < I; i += kWideThreads) A[(R - 1) * I + i] *= pscale;
+  if (tid == 0) {
+    A[(R - 1) * I + R - 1] = pbeta;
+    tau[R - 1] = pt;
+  }
+  __syncthreads();
   for (int c = R - 1; c >= 0; --c) {
     const double t = tau[c];
-    qrw_reflect(A, I, R, c, t, lane, wave);
+    qrw_reflect(A, I, R, c, t, 1.0, lane, wave);
     __syncthreads();
     for (int i = c + 1 + tid; i < I; i += kWideThreads) A[c * I + i] = -t * A[c * I + i];
     if (tid == 0) A[c * I + c] = 1.0 - t;

@@ -13,6 +13,8 @@ from .generators import (  # noqa: F401
     haar_stiefel,
     make_config,
     materialise,
+    mri_standin,
+    psnr,
     serving_trace,
     tucker,
     tucker_workload,

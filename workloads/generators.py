@@ -93,9 +93,11 @@ def tucker_workload(
     """Tucker low-rank tensor plus sparse corruption.
 
     ``scale``: None (leave the Tucker product as drawn), ``"rms"`` (scale the
-    low-rank part to unit root-mean-square) or ``"minmax"`` (map it affinely
-    onto [0, 1]).  ``mode``: ``"additive"`` adds U(value_range) at the chosen
-    positions; ``"impulse"`` replaces them by 0 or 1 with equal probability.
+    low-rank part to unit root-mean-square), ``"minmax"`` (map it affinely
+    onto [0, 1]) or ``"minmax255"`` (onto [0, 255], an 8-bit image range).
+    ``mode``: ``"additive"`` adds U(value_range) at the chosen positions;
+    ``"impulse"`` replaces them by 0 or 1 with equal probability; ``"replace"``
+    replaces them by U(value_range).
     """
     rng = np.random.default_rng(seed)
     dims = tuple(int(d) for d in dims)
@@ -106,6 +108,8 @@ def tucker_workload(
         L = L / math.sqrt(float(np.mean(L * L)))
     elif scale == "minmax":
         L = (L - L.min()) / (L.max() - L.min())
+    elif scale == "minmax255":
+        L = 255.0 * (L - L.min()) / (L.max() - L.min())
     elif scale is not None:
         raise ValueError(f"unknown scale {scale!r}")
     numel = L.size
@@ -120,6 +124,10 @@ def tucker_workload(
         S[pos] = vals
     elif mode == "impulse":
         vals = rng.integers(0, 2, size=pos.size).astype(np.float64)
+        S[pos] = vals - T[pos]
+        T[pos] = vals
+    elif mode == "replace":
+        vals = rng.uniform(value_range[0], value_range[1], size=pos.size)
         S[pos] = vals - T[pos]
         T[pos] = vals
     else:
@@ -137,6 +145,24 @@ def tucker_workload(
         meta={"seed": seed, "frac": frac, "core_ranks": tuple(core_ranks),
               "value_range": value_range, "mode": mode, "scale": scale},
     )
+
+
+def mri_standin(rho: float, seed: int = 17127000, core_ranks=(30, 30, 30),
+                precision: str = "fp64") -> Workload:
+    """Stand-in for the brain-MRI restoration of Section 5.2, whose data is not
+    available: a 181 x 217 x 181 tensor, here a Tucker tensor of rank
+    ``core_ranks`` (N(0, 1) core, Haar factors) mapped onto [0, 255], with a
+    fraction ``rho`` of the voxels replaced by U(0, 255); solved with
+    R_n = 40, epsilon 1e-5, maxiter 1000 as in the paper."""
+    return tucker_workload("mri", (181, 217, 181), core_ranks, rho, seed, value_range=(0.0, 255.0),
+                           mode="replace", scale="minmax255", ranks=(40, 40, 40), tol=1e-5,
+                           max_iter=1000, precision=precision)
+
+
+def psnr(X: np.ndarray, L: np.ndarray, peak: float = 255.0) -> float:
+    """Peak signal-to-noise ratio 10 log10(peak^2 / mean((X - L)^2)) in dB."""
+    mse = float(np.mean((np.asarray(X, dtype=np.float64) - L) ** 2))
+    return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
 
 
 def video_workload(
