@@ -11,7 +11,9 @@ their slots go to waiting requests.  A request's latency is its completion
 time minus its arrival time, queueing included.
 
 The numerical work of a solve is the same alone and in the mix: the batched
-kernels compute every problem with its own data and the same arithmetic.
+kernels compute every problem with its own data and the same arithmetic (up
+to the grouping of GEMM-M's partial sums, which differs for a solve launched
+alone with I_n > 176, where results agree to rounding).
 """
 
 from __future__ import annotations

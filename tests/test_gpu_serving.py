@@ -3,8 +3,10 @@
 A solve stepped inside a batch (grouped launches over several problems of
 different shapes and ranks) must give the same iterates as the same solve
 stepped alone -- bitwise, since every problem keeps its own data, block
-decomposition and reduction order -- and served results must match the FP64
-oracle within the FP32 bar.
+decomposition and reduction order (the shapes here stay below I_n = 177, where
+a solve launched alone would take GEMM-M's row-split instantiation and agree
+with its batched self to rounding only) -- and served results must match the
+FP64 oracle within the FP32 bar.
 """
 
 import numpy as np
