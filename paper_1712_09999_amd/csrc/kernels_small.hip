@@ -209,6 +209,21 @@ __device__ __forceinline__ bool jacobi_needed(const double (*A)[LD], int p, int 
   return b > 1e-150 && b * b > thr * thr * fabs(A[p][p]) * fabs(A[q][q]);
 }
 
+// Pairs whose 2 x 2 block lies wholly below the SVT threshold tau^2 on the
+// eigenvalues of S: both diagonal entries below t2h = tau^2 / 2 and the
+// coupling below t2r = tau^2 / (2 R).  They are not rotated.  W_f = F(S) with
+// F = 0 below tau^2, so a rotation inside that part cannot change W_f; once
+// every other pair has converged, the indices with diagonal below tau^2 / 2
+// span an invariant subspace whose eigenvalues are below tau^2 / 2 +
+// (R - 1) tau^2 / (2 R) < tau^2 (Gershgorin on that block), where f = 0 is
+// exact, and f_i computed from those diagonal entries is 0 as well.  This
+// saves the sweeps that would otherwise diagonalise directions the SVT
+// discards (the surplus R_n - r, and most directions while mu is small).
+__device__ __forceinline__ bool jacobi_discarded(double a, double d, double b, double t2h,
+                                                 double t2r) {
+  return a < t2h && d < t2h && fabs(b) < t2r;
+}
+
 // Rotation (c, s, t = s / c) that annihilates the off-diagonal b of the
 // symmetric 2x2 block [[a, b], [b, d]], in Rutishauser's form:
 // x = d - a, y = 2 b, r = hypot(x, y), w = |x| + r, c = w / hypot(w, y),
@@ -305,6 +320,8 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   }
   __syncthreads();
   const double thr = sizeof(S) == 4 ? 5.9604644775390625e-08 : 4.0e-16;
+  const double tau = pb.lam[n] / pb.sc->mu;
+  const double t2h = 0.5 * tau * tau, t2r = t2h / R;
   const int Rp = R + (R & 1);
   const int half = Rp / 2;
   const int m = Rp - 1;
@@ -314,7 +331,9 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
     int need = 0;
     {
       const int p = tid / kRT, q = tid % kRT;
-      if (p < q && q < R) need = jacobi_needed(Sb[cur], p, q, thr);
+      if (p < q && q < R)
+        need = jacobi_needed(Sb[cur], p, q, thr) &&
+               !jacobi_discarded(Sb[cur][p][p], Sb[cur][q][q], Sb[cur][p][q], t2h, t2r);
     }
     if (!__syncthreads_or(need)) break;
     sweeps = sweep + 1;
@@ -335,8 +354,10 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
           const double all = A[pl][pl], dll = A[ql][ql], bl = A[pl][ql];
           const double x00 = A[pk][pl], x01 = A[pk][ql], x10 = A[qk][pl], x11 = A[qk][ql];
           double ck, sk, tk, cl, sl, tl;
-          jacobi_rotation(akk, dkk, bk, qk < R, thr, ck, sk, tk);
-          jacobi_rotation(all, dll, bl, ql < R, thr, cl, sl, tl);
+          jacobi_rotation(akk, dkk, bk, qk < R && !jacobi_discarded(akk, dkk, bk, t2h, t2r), thr,
+                          ck, sk, tk);
+          jacobi_rotation(all, dll, bl, ql < R && !jacobi_discarded(all, dll, bl, t2h, t2r), thr,
+                          cl, sl, tl);
           // rows: J_k^T
           const double y00 = ck * x00 - sk * x10, y01 = ck * x01 - sk * x11;
           const double y10 = sk * x00 + ck * x10, y11 = sk * x01 + ck * x11;
@@ -369,7 +390,8 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
         const double all = A[pl][pl], dll = A[ql][ql], bl = A[pl][ql];
         const double wp = W[i][pl], wq = W[i][ql];
         double cl, sl, tl;
-        jacobi_rotation(all, dll, bl, ql < R, thr, cl, sl, tl);
+        jacobi_rotation(all, dll, bl, ql < R && !jacobi_discarded(all, dll, bl, t2h, t2r), thr,
+                        cl, sl, tl);
         W[i][pl] = cl * wp - sl * wq;
         W[i][ql] = sl * wp + cl * wq;
       }
@@ -378,7 +400,6 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
     }
   }
   if (tid == 0) pb.sc->eig_sweeps[n] = sweeps;
-  const double tau = pb.lam[n] / pb.sc->mu;
   if (tid < kRT) {
     double f = 0.0;
     if (tid < R) {
@@ -1178,6 +1199,8 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
   }
   __syncthreads();
   const double thr = sizeof(S) == 4 ? 5.9604644775390625e-08 : 4.0e-16;
+  const double tau = pb.lam[n] / pb.sc->mu;
+  const double t2h = 0.5 * tau * tau, t2r = t2h / R;
   const int Rp = R + (R & 1);
   const int half = Rp / 2;
   const int m = Rp - 1;
@@ -1202,7 +1225,11 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
     int need = 0;
     for (int e = tid; e < R * R; e += kWideThreads) {
       const int p = e / R, q = e - p * R;
-      if (p < q) need |= jacobi_needed(Sb[cur], p, q, thr) ? 1 : 0;
+      if (p < q)
+        need |= (jacobi_needed(Sb[cur], p, q, thr) &&
+                 !jacobi_discarded(Sb[cur][p][p], Sb[cur][q][q], Sb[cur][p][q], t2h, t2r))
+                    ? 1
+                    : 0;
     }
     if (!__syncthreads_or(need)) break;
     sweeps = sweep + 1;
@@ -1213,7 +1240,9 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
         int p, q;
         rr_pair(rd, tid, m, p, q);
         double c, sn, t;
-        jacobi_rotation(A[p][p], A[q][q], A[p][q], q < R, thr, c, sn, t);
+        const double app = A[p][p], aqq = A[q][q], apq = A[p][q];
+        jacobi_rotation(app, aqq, apq, q < R && !jacobi_discarded(app, aqq, apq, t2h, t2r), thr, c,
+                        sn, t);
         rot[tid][0] = c;
         rot[tid][1] = sn;
         rot[tid][2] = t;
@@ -1291,7 +1320,6 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
     }
   }
   if (tid == 0) pb.sc->eig_sweeps[n] = sweeps;
-  const double tau = pb.lam[n] / pb.sc->mu;
   if (tid < RT) {
     double f = 0.0;
     if (tid < R) {
