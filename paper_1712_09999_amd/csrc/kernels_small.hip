@@ -1005,8 +1005,122 @@ __device__ __forceinline__ void qrw_reflect(double* A, int I, int R, int c, doub
   }
 }
 
-// Householder QR of M_n (I x R, column-major in LDS) by one block, the same
-// reflectors as k_qr (LAPACK dgeqr2 / dorg2r conventions): wave w applies the
+// CholeskyQR2 for R_n up to kMR (the rank-wide form of k_qr_chol): two passes
+// of C = A^T A (FP64 MFMA, tile pairs a <= b), a right-looking Cholesky of C,
+// and A <- A R^-1, on A held column-major in LDS.  The factorisation keeps C's
+// rows unscaled (after step k, row k holds d_k r_k. / sqrt(d_k), d_k its
+// pivot), so a step is one rank-one update of the trailing triangle and one
+// barrier; the solve then takes p_j = (a_j - sum_{k<j} p_k c_kj) / d_j along
+// each row of A and q_j = p_j sqrt(d_j).  A pivot d_k <= floor2 c_kk (c_kk the
+// diagonal before the factorisation; 1e-12 in the first pass, 0.5 in the
+// second, as in k_qr_chol) abandons the attempt: A then still spans range(M_n)
+// (M_n itself, or the first pass's result) and the Householder QR takes over.
+// Returns whether both passes succeeded (block-uniform).
+constexpr int kCholW = kQrLdsW - kMR * (kMR + 1);  // I_n R_n limit: A and C share the LDS
+__device__ __forceinline__ bool qrw_cholqr2(double* A, double (*C)[kMR + 1], double* c0,
+                                            double* piv, int I, int R, int T, int tid, int lane,
+                                            int wave) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int kSlots = (kMR * (kMR + 1) / 2 + kWideThreads - 1) / kWideThreads;
+  // upper-triangle entries (i, j), i <= j < R, owned by this thread
+  int si[kSlots], sj[kSlots];
+  const int ntri = R * (R + 1) / 2;
+#pragma unroll
+  for (int u = 0; u < kSlots; ++u) {
+    int e = tid + kWideThreads * u, i = 0;
+    if (e >= ntri) e = ntri - 1;
+    while (e >= R - i) {
+      e -= R - i;
+      ++i;
+    }
+    si[u] = i;
+    sj[u] = i + e;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    const double floor2 = pass == 0 ? 1e-12 : 0.5;
+    // C = A^T A on the FP64 MFMA: lane (p, q) = (lane % 16, lane / 16) supplies
+    // A[k0 + q][16 a + p] for the A operand and A[k0 + q][16 b + p] for B.
+    const int p = lane & 15, q = lane >> 4;
+    const int np = T * (T + 1) / 2;
+    for (int pr = wave; pr < np; pr += kWideWaves) {
+      int a = 0, b = pr;
+      while (b >= T - a) {
+        b -= T - a;
+        ++a;
+      }
+      b += a;
+      const int ca = 16 * a + p, cb = 16 * b + p;
+      const double* xa = A + (int64_t)min(ca, R - 1) * I;
+      const double* xb = A + (int64_t)min(cb, R - 1) * I;
+      const bool oka = ca < R, okb = cb < R;
+      d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < I; k0 += 16) {
+        double va[4], vb[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int row = min(k0 + 4 * s4 + q, I - 1);
+          va[s4] = xa[row];
+          vb[s4] = xb[row];
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const bool rok = k0 + 4 * s4 + q < I;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((rok && oka) ? va[s4] : 0.0,
+                                                     (rok && okb) ? vb[s4] : 0.0, acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) C[16 * a + 4 * v + q][16 * b + p] = acc[v];
+    }
+    __syncthreads();
+    if (tid < R) c0[tid] = C[tid][tid];
+    __syncthreads();
+    bool ok = true;
+    for (int k = 0; k < R; ++k) {
+      const double d = C[k][k];
+      if (!(d > floor2 * c0[k])) {
+        ok = false;
+        break;
+      }
+      const double rd = 1.0 / d;
+      double ck[kSlots], cj[kSlots];
+#pragma unroll
+      for (int u = 0; u < kSlots; ++u) {
+        ck[u] = C[k][si[u]];
+        cj[u] = C[k][sj[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kSlots; ++u)
+        if (tid + kWideThreads * u < ntri && si[u] > k) C[si[u]][sj[u]] -= ck[u] * cj[u] * rd;
+      __syncthreads();
+    }
+    if (!ok) return false;
+    if (tid < R) piv[tid] = C[tid][tid];
+    __syncthreads();
+    for (int i = tid; i < I; i += kWideThreads) {
+      for (int j = 0; j < R; ++j) {
+        double a0 = A[j * I + i], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = 0;
+        for (; k + 4 <= j; k += 4) {
+          a0 = fma(-A[k * I + i], C[k][j], a0);
+          a1 = fma(-A[(k + 1) * I + i], C[k + 1][j], a1);
+          a2 = fma(-A[(k + 2) * I + i], C[k + 2][j], a2);
+          a3 = fma(-A[(k + 3) * I + i], C[k + 3][j], a3);
+        }
+        for (; k < j; ++k) a0 = fma(-A[k * I + i], C[k][j], a0);
+        A[j * I + i] = ((a0 + a1) + (a2 + a3)) / piv[j];
+      }
+      for (int j = 0; j < R; ++j) A[j * I + i] *= sqrt(piv[j]);
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// QR of M_n for R_n > kRT (column-major in LDS): CholeskyQR2 (qrw_cholqr2)
+// where I_n R_n <= kCholW and both passes keep their pivots, else Householder
+// QR by the whole block, the same reflectors as k_qr (LAPACK dgeqr2 / dorg2r
+// conventions): wave w applies the
 // reflector of a column step to columns c + 1 + w, c + 1 + w + kWideWaves, ...
 // (qrw_reflect), each a wave-wide dot product followed by its update, so the
 // waves need no barrier between the two.  A factorisation step has one
@@ -1029,70 +1143,77 @@ __global__ void __launch_bounds__(kWideThreads) k_qr_w(Batch<S> bt) {
   __shared__ double tau[kMR];
   __shared__ double red[kWideWaves];
   __shared__ double nrm[2];  // squared norm below the diagonal of the next column
+  __shared__ double c0[kMR], piv[kMR];
   for (int e = tid; e < I * R; e += kWideThreads) {
     const int c = e / I, i = e - c * I;
     A[e] = mb.M[((int64_t)(c / kRT) * I + i) * kRT + c % kRT];
   }
   __syncthreads();
-  {
-    double part = 0;
-    for (int i = 1 + tid; i < I; i += kWideThreads) {
-      const double x = A[i];
-      part += x * x;
-    }
-    part = block_sum_wide(part, red);
-    if (tid == 0) nrm[0] = part;
-    __syncthreads();
-  }
-  double pscale = 1.0, pbeta = 0.0, pt = 0.0;  // step c - 1, applied during step c
-  for (int c = 0; c < R; ++c) {
-    if (c > 0) {
-      if (pscale != 1.0)
-        for (int i = c + tid; i < I; i += kWideThreads) A[(c - 1) * I + i] *= pscale;
-      if (tid == 0) {
-        A[(c - 1) * I + c - 1] = pbeta;
-        tau[c - 1] = pt;
-      }
-    }
-    const double xnorm2 = nrm[c & 1];
-    const double alpha = A[c * I + c];
-    double t = 0, beta = alpha, scale = 0;
-    if (xnorm2 > 0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    qrw_reflect(A, I, R, c, t, scale, lane, wave);
-    if (wave == 0 && c + 1 < R) {
+  bool done = false;
+  if (I * R <= kCholW)
+    done = qrw_cholqr2(A, reinterpret_cast<double (*)[kMR + 1]>(A + kCholW), c0, piv, I, R, T, tid,
+                       lane, wave);
+  if (!done) {
+    {
       double part = 0;
-      for (int i = c + 2 + lane; i < I; i += 64) {
-        const double x = A[(c + 1) * I + i];
+      for (int i = 1 + tid; i < I; i += kWideThreads) {
+        const double x = A[i];
         part += x * x;
       }
-      part = wave_sum(part);
-      if (lane == 0) nrm[(c + 1) & 1] = part;
+      part = block_sum_wide(part, red);
+      if (tid == 0) nrm[0] = part;
+      __syncthreads();
     }
-    pscale = xnorm2 > 0 ? scale : 1.0;
-    pbeta = beta;
-    pt = t;
+    double pscale = 1.0, pbeta = 0.0, pt = 0.0;  // step c - 1, applied during step c
+    for (int c = 0; c < R; ++c) {
+      if (c > 0) {
+        if (pscale != 1.0)
+          for (int i = c + tid; i < I; i += kWideThreads) A[(c - 1) * I + i] *= pscale;
+        if (tid == 0) {
+          A[(c - 1) * I + c - 1] = pbeta;
+          tau[c - 1] = pt;
+        }
+      }
+      const double xnorm2 = nrm[c & 1];
+      const double alpha = A[c * I + c];
+      double t = 0, beta = alpha, scale = 0;
+      if (xnorm2 > 0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      qrw_reflect(A, I, R, c, t, scale, lane, wave);
+      if (wave == 0 && c + 1 < R) {
+        double part = 0;
+        for (int i = c + 2 + lane; i < I; i += 64) {
+          const double x = A[(c + 1) * I + i];
+          part += x * x;
+        }
+        part = wave_sum(part);
+        if (lane == 0) nrm[(c + 1) & 1] = part;
+      }
+      pscale = xnorm2 > 0 ? scale : 1.0;
+      pbeta = beta;
+      pt = t;
+      __syncthreads();
+    }
+    if (pscale != 1.0)
+      for (int i = R + tid; i < I; i += kWideThreads) A[(R - 1) * I + i] *= pscale;
+    if (tid == 0) {
+      A[(R - 1) * I + R - 1] = pbeta;
+      tau[R - 1] = pt;
+    }
     __syncthreads();
-  }
-  if (pscale != 1.0)
-    for (int i = R + tid; i < I; i += kWideThreads) A[(R - 1) * I + i] *= pscale;
-  if (tid == 0) {
-    A[(R - 1) * I + R - 1] = pbeta;
-    tau[R - 1] = pt;
-  }
-  __syncthreads();
-  for (int c = R - 1; c >= 0; --c) {
-    const double t = tau[c];
-    qrw_reflect(A, I, R, c, t, 1.0, lane, wave);
-    __syncthreads();
-    for (int i = c + 1 + tid; i < I; i += kWideThreads) A[c * I + i] = -t * A[c * I + i];
-    if (tid == 0) A[c * I + c] = 1.0 - t;
-    for (int i = tid; i < c; i += kWideThreads) A[c * I + i] = 0.0;
-    __syncthreads();
-  }
+    for (int c = R - 1; c >= 0; --c) {
+      const double t = tau[c];
+      qrw_reflect(A, I, R, c, t, 1.0, lane, wave);
+      __syncthreads();
+      for (int i = c + 1 + tid; i < I; i += kWideThreads) A[c * I + i] = -t * A[c * I + i];
+      if (tid == 0) A[c * I + c] = 1.0 - t;
+      for (int i = tid; i < c; i += kWideThreads) A[c * I + i] = 0.0;
+      __syncthreads();
+    }
+  }  // Householder
   for (int e = tid; e < I * T * kRT; e += kWideThreads) {
     const int t = e / (I * kRT), rem = e - t * I * kRT;
     const int i = rem / kRT, c = t * kRT + rem % kRT;
