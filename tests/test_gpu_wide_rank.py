@@ -185,3 +185,28 @@ def test_wide_rank_fig1_points_match_oracle(pt):
     assert list(info.rank[:3]) == pt["rank"]
     assert (rse <= 1e-3) == (pt["rse"] <= 1e-3)
     assert abs(rse - pt["rse"]) <= 1e-6 + 1e-3 * pt["rse"]
+
+
+def test_wide_rank_rank_deficient_m_fp64():
+    # An exactly rank-3 tensor without corruption and R_n = 20: M_n = G_n P_n^T
+    # is numerically rank deficient, the CholeskyQR2 pivots fail and the
+    # Householder QR completes the basis.  With the default tie-break the
+    # completion is not determined (reading R1: the Procrustes maximiser is not
+    # unique while V_n is rank deficient), so the oracle's and this path's
+    # iterates differ once it matters; what holds for any completion is checked:
+    # U_n orthonormal, the SVT ranks reaching the planted rank, and recovery.
+    dims, core, ranks = (40, 36, 34), (3, 3, 3), (20, 18, 17)
+    wl = workloads.tucker_workload("widedef", dims, core, 0.0, 17124700, scale="rms", ranks=ranks)
+    s = P.Solver(wl.T, ranks, precision="fp64", tol=1e-9, max_iter=2000, mu0=0.01)
+    for K in (2, 10, 25):
+        s.step(K - s.query().iterations)
+        orth = max(float(np.abs(s.export(P.Q_U, n).T @ s.export(P.Q_U, n) - np.eye(ranks[n])).max())
+                   for n in range(3))
+        print(f"rank-deficient M k={K}: orth {orth:.2e} rank {list(s.query().rank[:3])}", flush=True)
+        assert orth <= 1e-12
+    info = s.solve()
+    rse = rel(s.export(P.Q_X), wl.L)
+    print(f"rank-deficient M: k={info.iterations} converged={info.converged} "
+          f"rank={list(info.rank[:3])} RSE={rse:.2e}", flush=True)
+    assert info.converged == 1 and list(info.rank[:3]) == [3, 3, 3]
+    assert rse <= 1e-8
