@@ -1340,6 +1340,21 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
     blk_kl[e] = (k << 8) | (k + rem);
   }
   __syncthreads();
+  // this thread's slots, the same in every round: blocks (k, l) and
+  // eigenvector entries (row i, pair l)
+  int bk[kEigBU], bl[kEigBU], wi[kEigWU], wl[kEigWU];
+#pragma unroll
+  for (int u = 0; u < kEigBU; ++u) {
+    const int kl = blk_kl[min(tid + kWideThreads * u, nblk - 1)];
+    bk[u] = kl >> 8;
+    bl[u] = kl & 255;
+  }
+#pragma unroll
+  for (int u = 0; u < kEigWU; ++u) {
+    const int e = min(tid + kWideThreads * u, nwe - 1);
+    wi[u] = (e * mh) >> 16;
+    wl[u] = e - wi[u] * half;
+  }
   int sweeps = 0;
   int cur = 1;
   for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
@@ -1375,9 +1390,7 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
         double ck[kEigBU], sk[kEigBU], tk[kEigBU], cl[kEigBU], sl[kEigBU], x[kEigBU][4];
 #pragma unroll
         for (int u = 0; u < kEigBU; ++u) {
-          const int e = min(tid + kWideThreads * u, nblk - 1);
-          const int kl = blk_kl[e];
-          const int k = kl >> 8, l = kl & 255;
+          const int k = bk[u], l = bl[u];
           diag[u] = k == l;
           rr_pair(rd, k, m, pk[u], qk[u]);
           rr_pair(rd, l, m, pl[u], ql[u]);
@@ -1395,8 +1408,7 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
         double cw[kEigWU], sw[kEigWU], wp[kEigWU], wq[kEigWU];
 #pragma unroll
         for (int u = 0; u < kEigWU; ++u) {
-          const int e = min(tid + kWideThreads * u, nwe - 1);
-          const int i = (e * mh) >> 16, l = e - i * half;
+          const int i = wi[u], l = wl[u];
           iw[u] = i;
           rr_pair(rd, l, m, pw[u], qw[u]);
           cw[u] = rot[l][0];
