@@ -109,11 +109,13 @@ typedef struct {
                                        in the last SVT, per mode */
   size_t bytes_resident;            /* device memory held by the context */
   int eig_sweeps[PASD_MAX_ORDER];   /* Jacobi sweeps of the last Gram eigensolve, per mode */
-  double tol_effective;             /* tolerance of the last stopping test: max(tol, 8 u max|T - E|)
-                                       with u the unit roundoff of the state (2^-24 in FP32, where
-                                       the N low-rank copies cannot agree beyond a few ulps;
-                                       2^-11 with BF16 GEMM inputs, i.e. one BF16 unit roundoff of
-                                       max|T - E|, above the measured floor of ~1e-3 max|T - E|) */
+  double tol_effective;             /* tolerance of the last stopping test: max(tol, c u max|T - E|)
+                                       with u the unit roundoff of the state: c u = 16 * 2^-24 in
+                                       FP32, where the N low-rank copies, each a sum of R_n rounded
+                                       rank terms, cannot agree beyond a few ulps (measured floors
+                                       8-12 u max|T - E|); 8 * 2^-11 with BF16 GEMM inputs, i.e. one
+                                       BF16 unit roundoff of max|T - E|, above the measured floor of
+                                       ~1e-3 max|T - E|; 8 * 2^-53 in FP64 */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;
