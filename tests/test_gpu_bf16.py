@@ -52,6 +52,20 @@ def test_gemm_p_rounds_operands_to_bf16():
             assert np.array_equal(Pn.view(np.uint32), want.view(np.uint32)), n
 
 
+def test_gemm_p_rounds_operands_to_bf16_rank_tiles():
+    """The same pin for ranks above one 16-wide tile, where GEMM-P runs once
+    per rank tile: every tile's rows land in their place of P_n (R_1 = 33:
+    three tiles, the last one holding a single row)."""
+    dims, ranks = (40, 36, 34), (20, 33, 17)
+    T = (np.random.default_rng(5).standard_normal(dims) * 3.0).astype(np.float32)
+    with P.Solver(T, ranks, precision="bf16", tol=0.0, max_iter=1000) as s:
+        s.step(1)
+        for n, R in enumerate(ranks):
+            Pn = s.export(P.Q_P, n)
+            want = bf16_rne(_unfold_cols(T, n)[:R])
+            assert np.array_equal(Pn.view(np.uint32), want.view(np.uint32)), n
+
+
 def _proj_dist(U, V):
     return float(np.linalg.norm(U @ U.T - V @ V.T))
 
