@@ -1269,7 +1269,8 @@ __global__ void __launch_bounds__(256) k_tiebreak_w(Batch<S> bt) {
 // pair needs a rotation, then W_f = W diag(f) W^T and U W_f.  A round computes
 // the R'/2 rotations once (one thread per pair, into LDS), then every thread
 // applies them to its 2 x 2 blocks (k, l), k <= l, of the matrix (read from
-// one buffer, written to the other) and to its entries of the eigenvectors.
+// one buffer, written to the other; only the upper triangle is kept, which
+// halves the LDS writes of a round) and to its entries of the eigenvectors.
 // Each thread has fixed slots (block tid + kWideThreads u, eigenvector entry
 // tid + kWideThreads u)
 // whose indices are clamped into range, so that all reads of a phase are
@@ -1399,10 +1400,11 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
           tk[u] = rot[k][2];
           cl[u] = rot[l][0];
           sl[u] = rot[l][1];
-          x[u][0] = A[pk[u]][pl[u]];
-          x[u][1] = A[pk[u]][ql[u]];
-          x[u][2] = A[qk[u]][pl[u]];
-          x[u][3] = A[qk[u]][ql[u]];
+          // the rotated matrix is kept in its upper triangle only
+          x[u][0] = A[min(pk[u], pl[u])][max(pk[u], pl[u])];
+          x[u][1] = A[min(pk[u], ql[u])][max(pk[u], ql[u])];
+          x[u][2] = A[min(qk[u], pl[u])][max(qk[u], pl[u])];
+          x[u][3] = A[min(qk[u], ql[u])][max(qk[u], ql[u])];
         }
         int pw[kEigWU], qw[kEigWU], iw[kEigWU];
         double cw[kEigWU], sw[kEigWU], wp[kEigWU], wq[kEigWU];
@@ -1432,14 +1434,10 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
             z01 = 0.0;
             z10 = 0.0;
           }
-          B[pk[u]][pl[u]] = z00;
-          B[pk[u]][ql[u]] = z01;
-          B[qk[u]][pl[u]] = z10;
-          B[qk[u]][ql[u]] = z11;
-          B[pl[u]][pk[u]] = z00;
-          B[ql[u]][pk[u]] = z01;
-          B[pl[u]][qk[u]] = z10;
-          B[ql[u]][qk[u]] = z11;
+          B[min(pk[u], pl[u])][max(pk[u], pl[u])] = z00;
+          B[min(pk[u], ql[u])][max(pk[u], ql[u])] = z01;
+          B[min(qk[u], pl[u])][max(qk[u], pl[u])] = z10;
+          B[min(qk[u], ql[u])][max(qk[u], ql[u])] = z11;
         }
 #pragma unroll
         for (int u = 0; u < kEigWU; ++u) {
