@@ -287,7 +287,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(this build runs the solver on a single MI355X).", file=sys.stderr)
+              "(the solver runs on a single MI355X).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -46,7 +46,7 @@ enum pasd_status {
   PASD_OK = 0,
   PASD_NOT_CONVERGED = 1,    /* max_iter reached before the tolerance; results valid */
   PASD_ERR_INVALID_ARG = -1, /* bad pointer, dimension, rank, weight or option */
-  PASD_ERR_UNSUPPORTED = -2, /* valid input outside the sizes this build handles */
+  PASD_ERR_UNSUPPORTED = -2, /* valid input outside the sizes the library handles */
   PASD_ERR_OOM = -3,         /* device allocation failed */
   PASD_ERR_HIP = -4,         /* a HIP runtime call failed */
   PASD_ERR_NUMERIC = -5,     /* a NaN or infinity appeared in the iteration */
