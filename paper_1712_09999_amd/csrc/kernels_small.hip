@@ -181,6 +181,13 @@ __device__ __forceinline__ void rr_pair(int rd, int idx, int m, int& p, int& q) 
   }
 }
 
+// The round of the round-robin ordering (rr_pair, indices 0 .. m, m odd) in
+// which pair p < q is rotated: round p when q is the fixed index m, else the
+// round rd with p + q = 2 rd (mod m), i.e. rd = (p + q) (m + 1) / 2 mod m.
+__device__ __forceinline__ int rr_round(int p, int q, int m) {
+  return q == m ? p : (int)(((unsigned)(p + q) * (unsigned)((m + 1) / 2)) % (unsigned)m);
+}
+
 // 1/sqrt(a) and 1/a for normal a > 0: the hardware estimates (v_rsq_f64,
 // v_rcp_f64, relative error near 2^-23) refined by two Newton steps each,
 // h <- h + h (1 - a h^2) / 2 and r <- r + r (1 - a r), which square the error
@@ -260,6 +267,7 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   __shared__ double W[kRT][kRT + 1];
   __shared__ double T1[kRT][kRT + 1];
   __shared__ double fac[kRT];
+  __shared__ unsigned int rmask[2];  // rounds of the coming sweep with a pair to rotate
   __shared__ double Ul[kQrLds];
   double (*Sm)[kRT + 1] = Sb[0];
   {
@@ -327,6 +335,8 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
   const int m = Rp - 1;
   int sweeps = 0;
   int cur = 0;  // Sb[cur] holds the current matrix
+  if (tid < 2) rmask[tid] = 0u;
+  __syncthreads();
   for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
     int need = 0;
     {
@@ -334,10 +344,18 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
       if (p < q && q < R)
         need = jacobi_needed(Sb[cur], p, q, thr) &&
                !jacobi_discarded(Sb[cur][p][p], Sb[cur][q][q], Sb[cur][p][q], t2h, t2r);
+      if (need) atomicOr(&rmask[sweep & 1], 1u << rr_round(p, q, m));
     }
     if (!__syncthreads_or(need)) break;
     sweeps = sweep + 1;
+    // Rounds whose pairs all passed the check are skipped: a rotation in an
+    // earlier round can push one of their pairs back over the threshold, and
+    // the next check then starts another sweep, so the stopping criterion is
+    // unchanged.
+    const unsigned int mask = rmask[sweep & 1];
+    if (tid == 0) rmask[(sweep + 1) & 1] = 0u;  // every thread read it before this sweep's check
     for (int rd = 0; rd < m; ++rd) {
+      if (!((mask >> rd) & 1u)) continue;
       // Every thread derives the pairs and rotations it needs from the round
       // number and the current matrix, so a round is one read of Sb[cur], one
       // write of every entry of the other buffer, and one barrier.
@@ -1294,6 +1312,7 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
   __shared__ double rot[kMR / 2][3];
   __shared__ double fac[kMR];
   __shared__ int blk_kl[kEigBlk];  // (k << 8) | l of block slot e
+  __shared__ unsigned long long rmask[2];  // rounds of the coming sweep with a pair to rotate
   const int nb = mb.sblocks;
   for (int e = tid; e < RT * RT; e += kWideThreads) {
     const int r = e / RT, c = e - r * RT;
@@ -1358,19 +1377,28 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
   }
   int sweeps = 0;
   int cur = 1;
+  if (tid < 2) rmask[tid] = 0ull;
+  __syncthreads();
   for (int sweep = 0; sweep < 40 && R > 1; ++sweep) {
     int need = 0;
+    unsigned long long bits = 0ull;
     for (int e = tid; e < R * R; e += kWideThreads) {
       const int p = e / R, q = e - p * R;
-      if (p < q)
-        need |= (jacobi_needed(Sb[cur], p, q, thr) &&
-                 !jacobi_discarded(Sb[cur][p][p], Sb[cur][q][q], Sb[cur][p][q], t2h, t2r))
-                    ? 1
-                    : 0;
+      if (p < q &&
+          jacobi_needed(Sb[cur], p, q, thr) &&
+          !jacobi_discarded(Sb[cur][p][p], Sb[cur][q][q], Sb[cur][p][q], t2h, t2r)) {
+        need = 1;
+        bits |= 1ull << rr_round(p, q, m);
+      }
     }
+    if (bits) atomicOr(&rmask[sweep & 1], bits);
     if (!__syncthreads_or(need)) break;
     sweeps = sweep + 1;
+    // rounds whose pairs all passed the check are skipped (see k_eig)
+    const unsigned long long mask = rmask[sweep & 1];
+    if (tid == 0) rmask[(sweep + 1) & 1] = 0ull;
     for (int rd = 0; rd < m; ++rd) {
+      if (!((mask >> rd) & 1ull)) continue;
       const double (*A)[kMR + 1] = Sb[cur];
       double (*B)[kMR + 1] = Sb[cur ^ 1];
       if (tid < half) {
