@@ -45,6 +45,10 @@ extern "C" {
 enum pasd_status {
   PASD_OK = 0,
   PASD_NOT_CONVERGED = 1,    /* max_iter reached before the tolerance; results valid */
+  PASD_PRECISION_FLOOR = 2,  /* stopped without meeting tol: every residual fell below the
+                                rounding level of the state (pasd_info.tol_effective), where
+                                further iterations cannot lower it; results valid, not
+                                converged in the sense of Algorithm 1 */
   PASD_ERR_INVALID_ARG = -1, /* bad pointer, dimension, rank, weight or option */
   PASD_ERR_UNSUPPORTED = -2, /* valid input outside the sizes the library handles */
   PASD_ERR_OOM = -3,         /* device allocation failed */
@@ -57,10 +61,11 @@ enum pasd_precision {
   PASD_FP64 = 0,      /* FP64 state and arithmetic throughout */
   PASD_FP32 = 1,      /* FP32 state and unfolding GEMMs (FP32 MFMA); FP64 QR,
                          Gram, eigensolver, scalars */
-  PASD_BF16_GEMM = 2  /* FP32 state; both operands of the unfolding GEMMs
-                         (G_n and P_n for M_n, U_n and G_n for P_n) rounded
-                         to BF16 (round-to-nearest-even) with FP32
-                         accumulation on the matrix cores; FP64 QR, Gram,
+  PASD_BF16_GEMM = 2  /* FP32 state; the unfolding GEMMs (G_n P_n^T and U_n^T G_n)
+                         on the BF16 matrix cores: every FP32 operand is split
+                         into three BF16 terms (round-to-nearest-even) and each
+                         product is taken as six BF16 x BF16 terms with FP32
+                         accumulation, which keeps FP32 accuracy; FP64 QR, Gram,
                          eigensolver, scalars; FP32 elementwise pass */
 };
 
@@ -90,32 +95,38 @@ typedef struct {
 enum pasd_flags {
   PASD_FLAG_NO_GRAPH = 1,     /* launch every kernel directly instead of replaying a captured
                                  HIP graph of 16 iterations (same results, bitwise) */
-  PASD_FLAG_TIEBREAK_KEEP = 2 /* Procrustes tie-break of eq. (10) when V_n^k is rank deficient:
+  PASD_FLAG_TIEBREAK_KEEP = 2, /* Procrustes tie-break of eq. (10) when V_n^k is rank deficient:
                                  span U_n^{k+1} = range(G_n^k (V_n^k)^T) plus, on the directions
                                  where V_n^k vanishes, the previous U_n^k (the maximiser of
                                  eq. (10) nearest U_n^k).  Default (flag clear): span U_n^{k+1}
                                  = range(G_n^k (P_n^k)^T) with the pre-threshold P_n^k.  Both
                                  agree while every V_n^k has full rank; at k = 0 both keep U^0 */
+  PASD_FLAG_NO_FLOOR_STOP = 4  /* do not stop at the precision floor (done = 4): iterate until
+                                  Algorithm 1's test holds or max_iter */
 };
 
 /* Progress and status of a context. */
 typedef struct {
   int iterations;                   /* completed ADMM iterations k */
-  int converged;                    /* 1 once max_n residual[n] < tol */
-  int done;                         /* 0 running, 1 converged, 2 max_iter, 3 numeric error */
+  int converged;                    /* 1 once max_n residual[n] < tol (Algorithm 1, line 8) */
+  int done;                         /* 0 running, 1 converged, 2 max_iter, 3 numeric error,
+                                       4 stopped at the precision floor (see tol_effective) */
   double mu;                        /* current penalty mu^k */
   double residual[PASD_MAX_ORDER];  /* ||T - Z_n - E||_inf of the last iteration */
   int rank[PASD_MAX_ORDER];         /* #{singular values of U_n^T G_n above lambda_n/mu}
                                        in the last SVT, per mode */
   size_t bytes_resident;            /* device memory held by the context */
   int eig_sweeps[PASD_MAX_ORDER];   /* Jacobi sweeps of the last Gram eigensolve, per mode */
-  double tol_effective;             /* tolerance of the last stopping test: max(tol, c u max|T - E|)
-                                       with u the unit roundoff of the state: c u = 16 * 2^-24 in
-                                       FP32, where the N low-rank copies, each a sum of R_n rounded
-                                       rank terms, cannot agree beyond a few ulps (measured floors
-                                       8-12 u max|T - E|); 8 * 2^-11 with BF16 GEMM inputs, i.e. one
-                                       BF16 unit roundoff of max|T - E|, above the measured floor of
-                                       ~1e-3 max|T - E|; 8 * 2^-53 in FP64 */
+  double tol_effective;             /* precision floor of the last stopping test,
+                                       max(tol, c u max|T - E|) with u the unit roundoff of the
+                                       state: the N low-rank copies, each a sum of R_n rounded
+                                       rank terms, cannot agree beyond a few units of the last
+                                       place (measured floors 8-12 u max|T - E| in FP32), so
+                                       c u = 16 * 2^-24 for an FP32 state (also with split-BF16
+                                       GEMM operands) and 8 * 2^-53 in FP64.  A solve whose
+                                       residuals all fall below it but not below tol stops with
+                                       done = 4 and converged = 0 (PASD_PRECISION_FLOOR) unless
+                                       PASD_FLAG_NO_FLOOR_STOP is set */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;
@@ -166,9 +177,11 @@ int pasd_reset(pasd_ctx *ctx);
  * after a numeric error are skipped on the device. */
 int pasd_step(pasd_ctx *ctx, int n_iters);
 
-/* Iterate until converged or max_iter (synchronising), then fill info if
- * non-NULL.  Returns PASD_OK if converged, PASD_NOT_CONVERGED at max_iter,
- * PASD_ERR_NUMERIC on NaN/Inf. */
+/* Iterate until converged, max_iter or the precision floor (synchronising),
+ * then fill info if non-NULL.  Returns PASD_OK if Algorithm 1's test
+ * max_n ||T - Z_n - E||_inf < tol held, PASD_NOT_CONVERGED at max_iter,
+ * PASD_PRECISION_FLOOR when the residuals stalled below the state's rounding
+ * level but above tol, PASD_ERR_NUMERIC on NaN/Inf. */
 int pasd_solve(pasd_ctx *ctx, pasd_info *info);
 
 /* Synchronise and report progress. */

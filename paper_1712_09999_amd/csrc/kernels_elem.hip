@@ -379,12 +379,6 @@ __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
     fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk, xcd_split);
 }
 
-// BF16 GEMM inputs: the residual levels off near 1e-3 max|D| (measured on
-// the 200^3, video-shaped and serving workloads, fluctuating up to ~1.3e-3),
-// so u = 2^-11 makes the test certify one BF16 unit roundoff, 8 u = 2^-8, of
-// max|D|.
-constexpr double kBf16Level = 4.8828125e-04;
-
 // One wave: fold the residual slots (and clear them for the next iteration),
 // then lane 0 applies Algorithm 1, lines 7-8.
 template <typename S>
@@ -414,29 +408,30 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
   }
   if (lane != 0) return;
   for (int n = 0; n <= pb.N; ++n) res[n] = res_row[n < pb.N ? n : kMaxN];
-  // Stopping test of Algorithm 1 (line 8).  In FP32 state the N copies Z_n are
-  // each rebuilt from FP32 factors, so they disagree by a few units in the last
-  // place of |D|, and the residual T - Z_n - E cannot be certified below that:
-  // the test uses max(tol, c u max|D|), u the unit roundoff of the state type
-  // (2^-53 leaves the FP64 test unchanged in practice).  For the FP32 state
-  // c u = 16 * 2^-24: Z_n sums R_n rank terms rounded in FP32, and where the
-  // data's magnitude makes the allowance bind (values up to 255) the residual
-  // levels off at 8-12 u max|D| (measured at R_n = 16 and 40).  With BF16 GEMM
-  // inputs P_n carries the rounding of its operands, u is the measured relative
-  // level of the disagreement that leaves, and c = 8.
-  const double cu = pb.precision == PASD_BF16_GEMM ? 8.0 * kBf16Level
-                    : sizeof(S) == 4               ? 9.5367431640625e-07
-                                                   : 8.0 * 1.1102230246251565e-16;
+  // Stopping test of Algorithm 1 (line 8): converged when every residual is
+  // strictly below tol.  A rounded state cannot certify residuals below the
+  // rounding of its own values: the N copies Z_n are rebuilt from different
+  // rounded factors and disagree by a few units of the last place of |D|.
+  // When every residual is below that level, c u max|D| with u the unit
+  // roundoff of the state, but not below tol, the solve stops as "at the
+  // precision floor" (done = 4, converged stays 0) unless the caller asked to
+  // run on.  For an FP32 state c u = 16 * 2^-24: Z_n sums R_n rank terms
+  // rounded in FP32, and where the data's magnitude makes the floor bind
+  // (values up to 255) the residual levels off at 8-12 u max|D| (measured at
+  // R_n = 16 and 40).  The split-BF16 GEMM operands carry FP32 accuracy, so
+  // that mode shares the FP32 level; FP64 uses 8 * 2^-53.
+  const double cu = sizeof(S) == 4 ? 9.5367431640625e-07 : 8.0 * 1.1102230246251565e-16;
   const double dmax = res[pb.N];
-  const double tol_eff = pb.tol > 0.0 ? fmax(pb.tol, cu * dmax) : 0.0;  // tol 0: never stop
+  const double floor_lvl = pb.tol > 0.0 ? fmax(pb.tol, cu * dmax) : 0.0;  // tol 0: never stop
   sc->dmax = dmax;
-  sc->tol_eff = tol_eff;
-  bool conv = true, bad = false;
+  sc->tol_eff = floor_lvl;
+  bool conv = pb.tol > 0.0, at_floor = pb.tol > 0.0 && pb.floor_stop, bad = false;
   for (int n = 0; n < pb.N; ++n) {
     const double r = res[n];
     sc->residual[n] = r;
     pb.hist[(int64_t)sc->k * pb.N + n] = r;
-    if (!(r < tol_eff)) conv = false;
+    if (!(r < pb.tol)) conv = false;
+    if (!(r < floor_lvl)) at_floor = false;
     if (!isfinite(r)) bad = true;
   }
   if (!isfinite(dmax)) bad = true;
@@ -447,6 +442,8 @@ __global__ void __launch_bounds__(64) k_control(Batch<S> bt) {
   } else if (conv) {
     sc->converged = 1;
     sc->done = 1;
+  } else if (at_floor) {
+    sc->done = 4;
   } else if (sc->k >= pb.max_iter) {
     sc->done = 2;
   }

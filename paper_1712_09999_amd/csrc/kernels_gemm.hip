@@ -63,19 +63,63 @@ __device__ __forceinline__ d4v mma64(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// GEMM operand in the requested input precision: with BF the FP32 value is
-// rounded to the nearest BF16 (ties to even; infinities and NaN unchanged).
-// A product of two BF16 values is exact in FP32, so the FP32 MFMA then
-// computes exactly the BF16-input, FP32-accumulate product.
+// Split-BF16 products on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16).
+// Every FP32 operand x is written as x = h1 + h2 + h3 + e with h1 = bf16(x),
+// h2 = bf16(x - h1), h3 = bf16(x - h1 - h2), each BF16 rounding to nearest
+// even; both differences are exact in FP32 and |e| <= 2^-25 |x|.  The product
+// a b is taken as the six terms a1 b1 + a2 b1 + a1 b2 + a2 b2 + a1 b3 + a3 b1
+// (the dropped terms are below 2^-23 |a b|), each exact in FP32 and summed
+// with FP32 accumulation, so the GEMM keeps FP32 accuracy while every
+// multiplication runs on the BF16 matrix cores.
+//
+// The BF16 instruction takes 8 BF16 values of A and of B per lane where the
+// FP32 one takes one each: lane l supplies A[l % 16][k] and B[k][l % 16] for
+// the same eight contraction indices k, and the result layout is the f32
+// instruction's (row 4 (l/16) + v, column l % 16; checked on gfx950 with an
+// in-bounds probe).  One FP32 MFMA term A[m][k] B[k][n] becomes one BF16 MFMA
+// whose eight slots hold the six split products of that term (two slots zero);
+// the contraction index is still the lane group l / 16.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / NaN
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+struct Split3 {
+  uint32_t h1, h2, h3;  // BF16 bit patterns in the low 16 bits
+};
+
+__device__ __forceinline__ Split3 split3(float x) {
+  Split3 s;
+  s.h1 = bf16_rne_bits(x);
+  const float r1 = x - __uint_as_float(s.h1 << 16);
+  s.h2 = bf16_rne_bits(r1);
+  const float r2 = r1 - __uint_as_float(s.h2 << 16);
+  s.h3 = bf16_rne_bits(r2);
+  return s;
+}
+
+__device__ __forceinline__ f4v mma_split_bf16(float a, float b, f4v acc) {
+  const Split3 x = split3(a), y = split3(b);
+  // slots:  A = a1 a2 | a1 a2 | a1 a3 | 0 0,  B = b1 b1 | b2 b2 | b3 b1 | 0 0
+  const u4v va = u4v{x.h1 | (x.h2 << 16), x.h1 | (x.h2 << 16), x.h1 | (x.h3 << 16), 0u};
+  const u4v vb = u4v{y.h1 | (y.h1 << 16), y.h2 | (y.h2 << 16), y.h3 | (y.h1 << 16), 0u};
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, va),
+                                                 __builtin_bit_cast(bf16x8, vb), acc, 0, 0, 0);
+}
+
+// One MFMA term A[m][k] B[k][n] += a b: FP32 / FP64 matrix cores, or with BF
+// the split-BF16 form above (FP32 state only).
 template <bool BF, typename S>
-__device__ __forceinline__ S opnd(S x) {
+__device__ __forceinline__ typename MM<S>::acc_t mma_op(S a, S b, typename MM<S>::acc_t acc) {
   if constexpr (BF) {
-    static_assert(sizeof(S) == 4, "BF16 operands come from FP32 state");
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7f800000u) != 0x7f800000u) u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
-    return __uint_as_float(u);
+    static_assert(sizeof(S) == 4, "split-BF16 operands come from the FP32 state");
+    return mma_split_bf16(a, b, acc);
   } else {
-    return x;
+    return MM<S>::mma(a, b, acc);
   }
 }
 
@@ -174,7 +218,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc[t] = MM<S>::mma(opnd<BF>(u[k]), opnd<BF>(d[k][t] + y[k][t] * inv_mu), acc[t]);
+            acc[t] = mma_op<BF, S>((u[k]), (d[k][t] + y[k][t] * inv_mu), acc[t]);
       }
     } else {
       for (int i0 = kbeg; i0 < kend; i0 += 4) {
@@ -189,7 +233,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
           u = Us[(int64_t)i * kRT + p];
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = MM<S>::mma(opnd<BF>(u), opnd<BF>(gv[t]), acc[t]);
+        for (int t = 0; t < 4; ++t) acc[t] = mma_op<BF, S>((u), (gv[t]), acc[t]);
       }
     }
 #pragma unroll
@@ -249,7 +293,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc = MM<S>::mma(opnd<BF>(rowok ? d[k][t] + y[k][t] * inv_mu : S(0)), opnd<BF>(u[k][t]), acc);
+            acc = mma_op<BF, S>((rowok ? d[k][t] + y[k][t] * inv_mu : S(0)), (u[k][t]), acc);
       }
     } else {
       for (int i0 = 0; i0 < g.I; i0 += 16) {
@@ -265,7 +309,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const S u = (t < nv) ? Us[(int64_t)(i + t) * kRT + p] : S(0);
-          acc = MM<S>::mma(opnd<BF>(gv[t]), opnd<BF>(u), acc);
+          acc = mma_op<BF, S>((gv[t]), (u), acc);
         }
       }
     }
@@ -364,8 +408,8 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
             const bool ok = (rb0 + u) * 16 + p < g.I;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-              acc[u] = MM<S>::mma(opnd<BF>(ok ? dv[u][ks][t] + yv[u][ks][t] * inv_mu : S(0)),
-                                  opnd<BF>(pvv[t]), acc[u]);
+              acc[u] = mma_op<BF, S>((ok ? dv[u][ks][t] + yv[u][ks][t] * inv_mu : S(0)),
+                                  (pvv[t]), acc[u]);
           }
         }
       };
@@ -424,7 +468,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
           const bool ok = (ib0 + u) * 16 + p < g.I;
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            acc[u] = MM<S>::mma(opnd<BF>(ok ? dv[u][t] + yv[u][t] * inv_mu : S(0)), opnd<BF>(pvv[t]), acc[u]);
+            acc[u] = mma_op<BF, S>((ok ? dv[u][t] + yv[u][t] * inv_mu : S(0)), (pvv[t]), acc[u]);
         }
       }
       for (; st < send; st += kMWaves) {
@@ -463,7 +507,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
             load_g4<S>(pb.D, mb.Y, o, contig, nvalid, inv_mu, gv);
           }
 #pragma unroll
-          for (int t = 0; t < 4; ++t) acc[u] = MM<S>::mma(opnd<BF>(gv[t]), opnd<BF>(pv[t]), acc[u]);
+          for (int t = 0; t < 4; ++t) acc[u] = mma_op<BF, S>((gv[t]), (pv[t]), acc[u]);
         }
       }
       // reduce the waves and write rows i = 16(ib0+u) + 4q + v, column r = p
@@ -522,7 +566,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
             const bool ok = (c0 + c) * 64 + 4 * p < g.I;
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-              acc[c][t] = MM<S>::mma(opnd<BF>(ok ? dv[c][t] + yv[c][t] * inv_mu : S(0)), opnd<BF>(pv), acc[c][t]);
+              acc[c][t] = mma_op<BF, S>((ok ? dv[c][t] + yv[c][t] * inv_mu : S(0)), (pv), acc[c][t]);
           }
         }
       } else {
@@ -543,7 +587,7 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
               load_g4<S>(pb.D, mb.Y, o, contig, nv, inv_mu, gv);
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[c][t] = MM<S>::mma(opnd<BF>(gv[t]), opnd<BF>(pv), acc[c][t]);
+            for (int t = 0; t < 4; ++t) acc[c][t] = mma_op<BF, S>((gv[t]), (pv), acc[c][t]);
           }
         }
       }

@@ -46,7 +46,7 @@ struct ModeGeom {
 struct DevScalars {
   double mu;
   int k;
-  int done;  // 0 running, 1 converged, 2 max_iter, 3 numeric
+  int done;  // 0 running, 1 converged, 2 max_iter, 3 numeric, 4 precision floor
   int converged;
   int pad;
   double residual[kMaxN];              // residuals of the last completed iteration
@@ -102,6 +102,7 @@ struct Problem {
   int max_iter;
   int precision;
   int tiebreak_keep;  // PASD_FLAG_TIEBREAK_KEEP
+  int floor_stop;     // stop at the precision floor (PASD_FLAG_NO_FLOOR_STOP clear)
   double* hist;  // residual history [max_iter][N]
   // first block of every mode within this problem's grid, per kernel kind
   int kb[KB_COUNT][kMaxN + 1];

@@ -3,6 +3,7 @@
 // the kernels in kernels_*.hip.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -116,7 +117,7 @@ int validate_impl(const pasd_config* c) {
   if (c->max_iter < 1) return fail(PASD_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (c->precision != PASD_FP64 && c->precision != PASD_FP32 && c->precision != PASD_BF16_GEMM)
     return fail(PASD_ERR_INVALID_ARG, "unknown precision");
-  if (c->flags & ~(PASD_FLAG_NO_GRAPH | PASD_FLAG_TIEBREAK_KEEP))
+  if (c->flags & ~(PASD_FLAG_NO_GRAPH | PASD_FLAG_TIEBREAK_KEEP | PASD_FLAG_NO_FLOOR_STOP))
     return fail(PASD_ERR_INVALID_ARG, "unknown flag");
   return PASD_OK;
 }
@@ -133,7 +134,7 @@ struct Plan {
   int64_t numel;
 };
 
-void make_plan(const pasd_config* c, Plan& p) {
+void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
   const int N = c->order;
   const size_t es = c->precision == PASD_FP64 ? 8 : 4;
   int64_t numel = 1;
@@ -152,7 +153,7 @@ void make_plan(const pasd_config* c, Plan& p) {
     p.mblocks[n] = gemm_m_blocks(g, N);
     p.sblocks[n] = gram_blocks(g);
   }
-  p.off_T = p.L.add(numel * es);
+  p.off_T = own_T ? p.L.add(numel * es) : 0;  // T read in place when not owned
   p.off_D = p.L.add(numel * es);
   p.off_sc = p.L.add(sizeof(DevScalars));
   p.off_prob = p.L.add(std::max(sizeof(Problem<float>), sizeof(Problem<double>)));
@@ -182,7 +183,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   memset(&p, 0, sizeof(p));
   p.N = ctx->N;
   p.numel = ctx->numel;
-  p.T = reinterpret_cast<const S*>(b + pl.off_T);
+  p.T = reinterpret_cast<const S*>(ctx->T);
   p.D = reinterpret_cast<S*>(b + pl.off_D);
   p.sc = reinterpret_cast<DevScalars*>(b + pl.off_sc);
   p.hist = reinterpret_cast<double*>(b + pl.off_hist);
@@ -212,6 +213,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   p.max_iter = ctx->cfg.max_iter;
   p.precision = ctx->cfg.precision;
   p.tiebreak_keep = (ctx->cfg.flags & PASD_FLAG_TIEBREAK_KEEP) != 0 ? 1 : 0;
+  p.floor_stop = (ctx->cfg.flags & PASD_FLAG_NO_FLOOR_STOP) != 0 ? 0 : 1;
   // per-mode block offsets of the mode-grouped kernels, and the fused-pass share
   for (int n = 0; n <= ctx->N; ++n)
     for (int k = 0; k < KB_COUNT; ++k) p.kb[k][n] = 0;
@@ -371,7 +373,10 @@ void ensure_graph(pasd_ctx* ctx) {
 }
 
 int enqueue(pasd_ctx* ctx, int count, hipEvent_t* ev = nullptr) {
-  if (!ev && count >= kGraphIters && !ctx->graph_disabled) {
+  // The graph is captured and instantiated on the first enqueue of any
+  // length, so that a caller's warm-up (even one iteration) absorbs that cost
+  // and later calls replay it.
+  if (!ev && count > 0 && !ctx->graph_disabled) {
     ensure_graph(ctx);
     if (ctx->graph) {
       for (; count >= kGraphIters; count -= kGraphIters)
@@ -422,6 +427,89 @@ int copy_kind(int on_device) { return on_device ? hipMemcpyDeviceToDevice : hipM
 
 }  // namespace
 
+namespace {
+
+// Host part of a context: configuration, geometry, weights, device and
+// stream; touches no device.
+int ctx_init_host(pasd_ctx* ctx, const pasd_config* cfg, const Plan& pl) {
+  ctx->cfg = *cfg;
+  ctx->N = cfg->order;
+  int dev = cfg->device;
+  if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(PASD_ERR_HIP, "hipGetDevice failed (no GPU?)");
+  ctx->dev = dev;
+  ctx->stream = static_cast<hipStream_t>(cfg->stream);
+  ctx->graph_disabled = (cfg->flags & PASD_FLAG_NO_GRAPH) != 0;
+  ctx->elem = cfg->precision == PASD_FP64 ? 8 : 4;
+  ctx->numel = pl.numel;
+  for (int n = 0; n < ctx->N; ++n) {
+    const double J = (double)prod_except(cfg, n);
+    ctx->geom[n] = pl.geom[n];
+    ctx->lam[n] = cfg->lambda[n] > 0 ? cfg->lambda[n]
+                                     : sqrt(std::max((double)cfg->dims[n], J)) / ctx->N;
+    ctx->mblocks[n] = pl.mblocks[n];
+    ctx->sblocks[n] = pl.sblocks[n];
+  }
+  for (int n = 0; n < ctx->N; ++n) ctx->alpha[n] = cfg->alpha[n] > 0 ? cfg->alpha[n] : ctx->lam[n];
+  return PASD_OK;
+}
+
+// Zero `bytes` (a multiple of 16, 16-byte aligned) with a plain kernel rather
+// than a memset node, so that the clearing is an ordinary launch wherever the
+// caller's stream is.
+__global__ void __launch_bounds__(256) k_zero(uint4* p, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = uint4{0u, 0u, 0u, 0u};
+}
+
+hipError_t zero_async(void* p, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  const size_t blocks = std::min<size_t>(std::max<size_t>(1, (n16 + 255) / 256), 4096);
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
+
+// Device part: lay the solver state out in `base` (pl.L.total bytes of device
+// memory of ctx->dev), clear it, upload the descriptors, bring T in (copied
+// into the plan's T slot, or read in place from the caller's device buffer
+// when T_in_place) and run the initialisation of Algorithm 1.  Asynchronous
+// on ctx->stream.
+int ctx_init_device(pasd_ctx* ctx, const Plan& pl, void* base, const void* T, int T_on_device,
+                    bool T_in_place) {
+  ctx->base = base;
+  ctx->T = T_in_place ? const_cast<void*>(T) : static_cast<char*>(base) + pl.off_T;
+  // zero the whole state once: the padding rows of P_n and columns of the
+  // factors are read by the unrolled kernels and must stay zero
+  hipError_t e = zero_async(base, pl.L.total, ctx->stream);
+  if (e != hipSuccess) return fail(PASD_ERR_HIP, std::string("clearing state: ") + hipGetErrorString(e));
+  ctx->dev_prob = static_cast<char*>(base) + pl.off_prob;
+  if (ctx->cfg.precision == PASD_FP64) {
+    fill_problem<double>(ctx, pl, ctx->pd);
+    fill_views<double>(ctx, pl, ctx->pd, ctx->vd);
+    e = upload_problem<double>(ctx, ctx->pd);
+  } else {
+    fill_problem<float>(ctx, pl, ctx->pf);
+    fill_views<float>(ctx, pl, ctx->pf, ctx->vf);
+    e = upload_problem<float>(ctx, ctx->pf);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(PASD_ERR_HIP, std::string("problem upload: ") + hipGetErrorString(e));
+  if (!T_in_place) {
+    e = hipMemcpyAsync(ctx->T, T, (size_t)ctx->numel * ctx->elem,
+                       (hipMemcpyKind)copy_kind(T_on_device), ctx->stream);
+    if (e != hipSuccess) return fail(PASD_ERR_HIP, std::string("copy of T: ") + hipGetErrorString(e));
+  }
+  if (ctx->cfg.precision == PASD_FP64)
+    launch_init<double>(ctx->pd, ctx->cfg.mu0, ctx->stream);
+  else
+    launch_init<float>(ctx->pf, ctx->cfg.mu0, ctx->stream);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(PASD_ERR_HIP, std::string("initialisation: ") + hipGetErrorString(e));
+  return PASD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int pasd_config_init(pasd_config* cfg) {
@@ -462,77 +550,29 @@ int pasd_create(const pasd_config* cfg, const void* T, int T_on_device, pasd_ctx
   if (rc != PASD_OK) return rc;
   if (!T) return fail(PASD_ERR_INVALID_ARG, "T is NULL");
   pasd_ctx* ctx = new pasd_ctx();
-  ctx->cfg = *cfg;
-  ctx->N = cfg->order;
-  int dev = cfg->device;
-  if (dev < 0) {
-    if (hipGetDevice(&dev) != hipSuccess) {
-      delete ctx;
-      return fail(PASD_ERR_HIP, "hipGetDevice failed (no GPU?)");
-    }
-  }
-  ctx->dev = dev;
-  ctx->stream = static_cast<hipStream_t>(cfg->stream);
-  ctx->graph_disabled = (cfg->flags & PASD_FLAG_NO_GRAPH) != 0;
-  ctx->elem = cfg->precision == PASD_FP64 ? 8 : 4;
   Plan pl;
   make_plan(cfg, pl);
-  ctx->numel = pl.numel;
-  const int64_t numel = pl.numel;
-  for (int n = 0; n < ctx->N; ++n) {
-    const double J = (double)prod_except(cfg, n);
-    ctx->geom[n] = pl.geom[n];
-    ctx->lam[n] = cfg->lambda[n] > 0 ? cfg->lambda[n]
-                                     : sqrt(std::max((double)cfg->dims[n], J)) / ctx->N;
-    ctx->mblocks[n] = pl.mblocks[n];
-    ctx->sblocks[n] = pl.sblocks[n];
+  rc = ctx_init_host(ctx, cfg, pl);
+  if (rc != PASD_OK) {
+    delete ctx;
+    return rc;
   }
-  for (int n = 0; n < ctx->N; ++n) ctx->alpha[n] = cfg->alpha[n] > 0 ? cfg->alpha[n] : ctx->lam[n];
-  DeviceGuard guard(dev);
+  DeviceGuard guard(ctx->dev);
   hipError_t e = hipMalloc(&ctx->base, pl.L.total);
   if (e != hipSuccess) {
     delete ctx;
     return fail(e == hipErrorOutOfMemory ? PASD_ERR_OOM : PASD_ERR_HIP,
                 std::string("hipMalloc of solver state: ") + hipGetErrorString(e));
   }
-  e = hipMalloc(&ctx->scratch_out, (size_t)numel * ctx->elem);
+  e = hipMalloc(&ctx->scratch_out, (size_t)ctx->numel * ctx->elem);
   if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->host_sc, sizeof(DevScalars), hipHostMallocDefault);
   if (e != hipSuccess) {
     pasd_destroy(ctx);
     return fail(e == hipErrorOutOfMemory ? PASD_ERR_OOM : PASD_ERR_HIP,
                 std::string("allocation: ") + hipGetErrorString(e));
   }
-  ctx->bytes = pl.L.total + (size_t)numel * ctx->elem;
-  ctx->T = static_cast<char*>(ctx->base) + pl.off_T;
-  // zero the whole state once: the padding rows of P_n and columns of the
-  // factors are read by the unrolled kernels and must stay zero
-  e = hipMemsetAsync(ctx->base, 0, pl.L.total, ctx->stream);
-  if (e != hipSuccess) {
-    pasd_destroy(ctx);
-    return fail(PASD_ERR_HIP, std::string("clearing state: ") + hipGetErrorString(e));
-  }
-  ctx->dev_prob = static_cast<char*>(ctx->base) + pl.off_prob;
-  if (cfg->precision == PASD_FP64) {
-    fill_problem<double>(ctx, pl, ctx->pd);
-    fill_views<double>(ctx, pl, ctx->pd, ctx->vd);
-    e = upload_problem<double>(ctx, ctx->pd);
-  } else {
-    fill_problem<float>(ctx, pl, ctx->pf);
-    fill_views<float>(ctx, pl, ctx->pf, ctx->vf);
-    e = upload_problem<float>(ctx, ctx->pf);
-  }
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) {
-    pasd_destroy(ctx);
-    return fail(PASD_ERR_HIP, std::string("problem upload: ") + hipGetErrorString(e));
-  }
-  e = hipMemcpyAsync(ctx->T, T, (size_t)numel * ctx->elem, (hipMemcpyKind)copy_kind(T_on_device),
-                     ctx->stream);
-  if (e != hipSuccess) {
-    pasd_destroy(ctx);
-    return fail(PASD_ERR_HIP, std::string("copy of T: ") + hipGetErrorString(e));
-  }
-  rc = pasd_reset(ctx);
+  ctx->bytes = pl.L.total + (size_t)ctx->numel * ctx->elem;
+  rc = ctx_init_device(ctx, pl, ctx->base, T, T_on_device, false);
   if (rc == PASD_OK) {
     e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) rc = fail(PASD_ERR_HIP, std::string("create: ") + hipGetErrorString(e));
@@ -590,6 +630,7 @@ int pasd_solve(pasd_ctx* ctx, pasd_info* info) {
   switch (ctx->host_sc->done) {
     case 1: return PASD_OK;
     case 2: return PASD_NOT_CONVERGED;
+    case 4: return PASD_PRECISION_FLOOR;
     default: return fail(PASD_ERR_NUMERIC, "NaN or infinity in the iteration");
   }
 }

@@ -22,6 +22,7 @@ MAX_RANK = 64
 
 OK = 0
 NOT_CONVERGED = 1
+PRECISION_FLOOR = 2
 ERR_INVALID_ARG = -1
 ERR_UNSUPPORTED = -2
 ERR_OOM = -3
@@ -32,6 +33,7 @@ ERR_STATE = -6
 FP64, FP32, BF16_GEMM = 0, 1, 2
 FLAG_NO_GRAPH = 1
 FLAG_TIEBREAK_KEEP = 2
+FLAG_NO_FLOOR_STOP = 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16_GEMM}
 
 Q_E, Q_Y, Q_Z, Q_X, Q_U, Q_P, Q_UF, Q_SCALARS, Q_D, Q_WEV, Q_FAC = range(11)
@@ -132,7 +134,7 @@ def make_config(dims: Sequence[int], ranks: Sequence[int], lam: Optional[Sequenc
                 alpha: Optional[Sequence[float]] = None, mu0: float = 1e-4, mu_max: float = 1e10,
                 rho: float = 1.1, tol: float = 1e-5, max_iter: int = 1000,
                 precision="fp64", device: int = -1, stream: int = 0,
-                graphs: bool = True, tiebreak: str = "pre") -> Config:
+                graphs: bool = True, tiebreak: str = "pre", floor_stop: bool = True) -> Config:
     c = Config()
     lib().pasd_config_init(ctypes.byref(c))
     c.order = len(dims)
@@ -153,7 +155,8 @@ def make_config(dims: Sequence[int], ranks: Sequence[int], lam: Optional[Sequenc
     c.stream = int(stream) if stream else None
     if tiebreak not in ("pre", "keep"):
         raise ValueError("tiebreak must be 'pre' or 'keep'")
-    c.flags = (0 if graphs else FLAG_NO_GRAPH) | (FLAG_TIEBREAK_KEEP if tiebreak == "keep" else 0)
+    c.flags = ((0 if graphs else FLAG_NO_GRAPH) | (FLAG_TIEBREAK_KEEP if tiebreak == "keep" else 0)
+               | (0 if floor_stop else FLAG_NO_FLOOR_STOP))
     return c
 
 
@@ -177,7 +180,7 @@ class Solver:
     def __init__(self, T, ranks: Sequence[int], *, lam=None, alpha=None, mu0: float = 1e-4,
                  mu_max: float = 1e10, rho: float = 1.1, tol: float = 1e-5, max_iter: int = 1000,
                  precision="fp64", device: Optional[int] = None, stream: int = 0,
-                 graphs: bool = True, tiebreak: str = "pre"):
+                 graphs: bool = True, tiebreak: str = "pre", floor_stop: bool = True):
         import torch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         sdt = torch.float64 if self.precision == FP64 else torch.float32
@@ -193,7 +196,7 @@ class Solver:
         self.torch_dtype = sdt
         self.np_dtype = _state_dtype(self.precision)
         self.cfg = make_config(self.dims, ranks, lam, alpha, mu0, mu_max, rho, tol, max_iter,
-                               self.precision, self.device, stream, graphs, tiebreak)
+                               self.precision, self.device, stream, graphs, tiebreak, floor_stop)
         h = ctypes.c_void_p()
         torch.cuda.synchronize(T.device)
         _check(lib().pasd_create(ctypes.byref(self.cfg), ctypes.c_void_p(T.data_ptr()), 1,
@@ -235,7 +238,7 @@ class Solver:
     def solve(self) -> Info:
         info = Info()
         code = lib().pasd_solve(self.handle, ctypes.byref(info))
-        _check(code, allow=(OK, NOT_CONVERGED))
+        _check(code, allow=(OK, NOT_CONVERGED, PRECISION_FLOOR))
         return info
 
     def profile(self, n_iters: int):
@@ -317,3 +320,4 @@ def query_batch(solvers: List[Solver]) -> List[Info]:
     infos = (Info * len(solvers))()
     _check(lib().pasd_query_batch(arr, len(solvers), infos))
     return list(infos)
+

@@ -46,6 +46,7 @@ class Result:
     completed: float
     iterations: int
     converged: bool
+    done: int = 0
     X: object = None
     E: object = None
 
@@ -117,7 +118,7 @@ class Server:
                         X, E = s.result()
                     done_t = time.perf_counter() - t0
                     results.append(Result(req.rid, req.arrival if realtime else 0.0, adm, done_t,
-                                          info.iterations, bool(info.converged), X, E))
+                                          info.iterations, bool(info.converged), info.done, X, E))
                     s.close()
                     used -= fp
                 else:
@@ -134,7 +135,39 @@ def latency_summary(results: List[Result]) -> dict:
     return {"count": len(results), "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
             "solves_per_s": len(results) / wall if wall > 0 else float("inf"),
-            "converged": int(sum(r.converged for r in results))}
+            "converged": int(sum(r.converged for r in results)),
+            "floor": int(sum(r.done == 4 for r in results))}
+
+
+def service_times(requests: List[Request], precision: str = "fp32", device: int = 0) -> Dict[int, float]:
+    """Seconds each request takes when served alone by plain calls: context
+    creation (allocation and the copy of T), pasd_solve, the copy-out of X and
+    E, and release."""
+    import torch
+    out = {}
+    for req in requests:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = P.Solver(req.T, req.ranks, tol=req.tol, max_iter=req.max_iter, precision=precision,
+                     device=device)
+        s.solve()
+        s.result()
+        s.close()
+        torch.cuda.synchronize()
+        out[req.rid] = time.perf_counter() - t0
+    return out
+
+
+def sequential_replay(requests: List[Request], service: Dict[int, float]) -> List[Result]:
+    """The trace served one request at a time, service starting at
+    max(arrival, previous completion), with measured service times."""
+    results = []
+    clock = 0.0
+    for req in sorted(requests, key=lambda r: r.arrival):
+        start = max(clock, req.arrival)
+        clock = start + service[req.rid]
+        results.append(Result(req.rid, req.arrival, start, clock, 0, True))
+    return results
 
 
 def sequential(requests: List[Request], precision: str = "fp32", device: int = 0) -> List[Result]:

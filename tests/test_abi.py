@@ -75,9 +75,9 @@ def test_validation_codes(kw, code):
 
 def test_unknown_flag_rejected():
     c = _cfg()
-    c.flags = 4
+    c.flags = 8
     assert pasd.validate(c) == binding.ERR_INVALID_ARG
-    c.flags = binding.FLAG_NO_GRAPH | binding.FLAG_TIEBREAK_KEEP
+    c.flags = binding.FLAG_NO_GRAPH | binding.FLAG_TIEBREAK_KEEP | binding.FLAG_NO_FLOOR_STOP
     assert pasd.validate(c) == 0
 
 
@@ -108,3 +108,4 @@ def test_create_rejects_bad_arguments_without_gpu():
     rc = pasd.lib().pasd_create(ctypes.byref(good), None, 0, ctypes.byref(h))
     assert rc == binding.ERR_INVALID_ARG and not h.value
     pasd.lib().pasd_destroy(None)  # NULL-safe
+

@@ -62,8 +62,8 @@ def test_mri_standin_full_solve_matches_oracle(wl, precision):
     print(f"mri {precision}: k={info.iterations} (oracle {GOLDEN['iterations']}) "
           f"rank={list(info.rank[:3])} (oracle {GOLDEN['rank']}) PSNR={p:.3f} dB "
           f"(oracle {GOLDEN['psnr_db']:.3f}, observed {GOLDEN['psnr_observed_db']:.2f})", flush=True)
-    assert info.converged == 1
     if precision == "fp64":
+        assert info.converged == 1
         # the oracle restores the stand-in to ~2e-9 RMS (PSNR ~222 dB); the GPU
         # iterate differs from the oracle's at the 1e-13 level, which moves the
         # PSNR by hundredths of a dB
@@ -71,6 +71,11 @@ def test_mri_standin_full_solve_matches_oracle(wl, precision):
         assert abs(info.iterations - GOLDEN["iterations"]) <= 1
         assert list(info.rank[:3]) == GOLDEN["rank"]
     else:
-        # FP32 state: the restoration is bounded by FP32 rounding of X (~1e-7
-        # relative), i.e. PSNR near 150 dB
+        # FP32 state on values up to 255: the residual cannot be certified
+        # below the FP32 rounding level (tol_effective ~ 2e-4 > tol), so the
+        # solve ends at the precision floor (or converged), never claiming
+        # convergence above tol; the restoration is bounded by FP32 rounding of
+        # X (~1e-7 relative), i.e. PSNR near 150 dB
+        r = max(info.residual[:3])
+        assert info.done in (1, 4) and (info.converged == 1) == (r < GOLDEN["tol"])
         assert p >= 120.0

@@ -33,48 +33,7 @@ def _need_gpu():
 
 from paper_1712_09999_amd import pasd as P  # noqa: E402
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5}
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
-
-
-def _gpu(T, ranks, precision, **kw):
-    dt = np.float64 if precision == "fp64" else np.float32
-    args = dict(tol=0.0, max_iter=100000)
-    args.update(kw)
-    return P.Solver(np.ascontiguousarray(T.astype(dt)), ranks, precision=precision, **args)
-
-
-def _compare(st, s, precision, label=""):
-    bar = TOL[precision]
-    N = st.T.ndim
-    info = s.query()
-    assert info.iterations == st.k, (label, info.iterations, st.k)
-    X_o, E_o = pasd_output(st)
-    X_g = s.export(P.Q_X).astype(np.float64)
-    E_g = s.export(P.Q_E).astype(np.float64)
-    errs = {"X": rel(X_g, X_o), "E": rel(E_g, E_o)}
-    for n in range(N):
-        errs[f"Z{n}"] = rel(s.export(P.Q_Z, n).astype(np.float64), st.Z[n])
-        errs[f"Y{n}"] = rel(s.export(P.Q_Y, n).astype(np.float64), st.Y[n])
-        U = s.export(P.Q_U, n)
-        errs[f"UU{n}"] = rel(U @ U.T, st.U[n] @ st.U[n].T)
-        assert info.rank[n] == st.rank[n] or precision != "fp64", (label, n, info.rank[n], st.rank[n])
-    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        lim = bar * (10 if k.startswith("Y") else 1)
-        if k.startswith("Y") and precision == "fp32":
-            # Y += mu (D - Z): the FP32 rounding of D and Z (~6e-8 |Z|) enters
-            # Y multiplied by mu, which reaches ~150 by the end of c1; the
-            # multipliers therefore carry ~mu * 6e-8 absolute error per step.
-            lim = 1e-3
-        if k.startswith("UU"):
-            lim = bar * 100
-        assert v <= lim, (label, k, v)
-    return errs
+from parity_util import TOL, _compare, _gpu, rel  # noqa: E402
 
 
 # --------------------------------------------------------------------------- c1 trajectory
@@ -295,3 +254,43 @@ def test_nan_input_reports_numeric_error():
         s.solve()
     assert ei.value.code == P.ERR_NUMERIC
     assert s.query().done == 3
+
+
+# --------------------------------------------------------------------------- weights and the penalty cap
+
+def test_unequal_output_weights_on_a_non_cube():
+    """alpha_n of the output X = sum alpha_n Z_n / sum alpha_n (reading:
+    alpha_n = lambda_n by default) passed explicitly and unequal on a
+    non-cubic tensor, where the copies Z_n differ before convergence: a wrong
+    weighting of the output is visible at 1e-10."""
+    wl = workloads.tucker_workload("alpha", (30, 22, 14), (3, 4, 2), 0.08, 4711,
+                                   value_range=(-5, 5), scale="rms")
+    alpha = (0.5, 2.0, 7.0)
+    lam = (3.0, 2.5, 4.0)
+    st = pasd_init(wl.T, wl.ranks, lam=lam, alpha=alpha, mu0=0.01)
+    pasd_iterate(st, 25)
+    s = _gpu(wl.T, wl.ranks, "fp64", lam=lam, alpha=alpha, mu0=0.01)
+    s.step(25)
+    errs = _compare(st, s, "fp64", "alpha/lambda explicit k=25")
+    # the weighting matters here: the equal-weight mean differs from X
+    X_eq = sum(st.Z) / 3.0
+    X_o, _ = pasd_output(st)
+    assert rel(X_eq, X_o) > 1e-6
+    assert errs["X"] <= 1e-10
+
+
+def test_penalty_cap_binds():
+    """mu = min(rho mu, mu_max) (Algorithm 1, line 7) with a cap reached after
+    a few iterations (mu0 = 0.5, mu_max = 2, rho = 1.5): both sides run 30
+    iterations at the cap; a wrong cap or an update order that skips it would
+    change the multipliers, the shrinkage threshold and the SVT threshold."""
+    wl = workloads.tucker_workload("cap", (26, 20, 18), (3, 3, 3), 0.1, 4712,
+                                   value_range=(-5, 5), scale="rms")
+    kw = dict(mu0=0.5, mu_max=2.0, rho=1.5)
+    st = pasd_init(wl.T, wl.ranks, **kw)
+    pasd_iterate(st, 30)
+    assert st.mu == 2.0
+    s = _gpu(wl.T, wl.ranks, "fp64", **kw)
+    s.step(30)
+    assert float(s.export(P.Q_SCALARS)[1]) == 2.0
+    _compare(st, s, "fp64", "mu_max binds k=30")
