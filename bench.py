@@ -325,7 +325,8 @@ def _solve_row(T, ranks, prec, tol, max_iter, L=None, mask=None, reps=1):
     if L is not None:
         row["rse_vs_planted"] = _rel(X, L)
     if mask is not None:
-        supp = E != 0
+        # recovered support: |E| above the level the last stopping test certified
+        supp = np.abs(E) > max(tol, info.tol_effective)
         row["support_exact"] = bool(np.array_equal(supp, mask))
         row["support_mismatches"] = int(np.count_nonzero(supp != mask))
     return row, X, E
