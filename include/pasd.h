@@ -233,6 +233,32 @@ int pasd_profile(pasd_ctx *ctx, int n_iters, double *ms, int *launches);
  * (serving loops poll every resident solve after each batched step). */
 int pasd_query_batch(pasd_ctx *const *ctxs, int count, pasd_info *infos);
 
+/* One whole solve that allocates nothing, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).
+ * Equivalent to pasd_create + pasd_solve + pasd_get_result + pasd_destroy on
+ * a context with PASD_FLAG_NO_GRAPH (the same kernels in the same order,
+ * launched directly on cfg->stream, so the same results), except that T is
+ * read in place and the solver state lives in a static device array of
+ * pasd_static_scratch_bytes() bytes (32 MiB) that the library holds on every
+ * GPU it runs on until the process ends.
+ *   T    device pointer, numel elements of the state dtype, row-major; only
+ *        read, and must stay valid until the call returns.
+ *   X, E device pointers receiving the output of Algorithm 1 (numel elements
+ *        of the state dtype each); either may be NULL.
+ *   info filled as by pasd_solve when non-NULL.
+ * Returns pasd_solve's status (results are written for PASD_OK,
+ * PASD_NOT_CONVERGED and PASD_PRECISION_FLOOR), PASD_ERR_INVALID_ARG, or
+ * PASD_ERR_UNSUPPORTED when the state does not fit the static array (it takes
+ * pasd_footprint(cfg) minus two tensors of numel elements).  Calls no
+ * hipMalloc, hipFree, graph instantiation or other allocating routine; the
+ * state is cleared at the start of every call.  Synchronising.  All calls on
+ * one GPU share its array: calls that overlap on the same GPU (from several
+ * threads or streams) race and must be serialised by the caller. */
+int pasd_solve_static(const pasd_config *cfg, const void *T, void *X, void *E, pasd_info *info);
+
+/* Size in bytes of the static device array behind pasd_solve_static. */
+size_t pasd_static_scratch_bytes(void);
+
 /* Release everything the context holds.  NULL-safe. */
 void pasd_destroy(pasd_ctx *ctx);
 

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -973,6 +974,92 @@ int pasd_profile(pasd_ctx* ctx, int n_iters, double* ms, int* launches) {
   }
   for (size_t i = 0; i < made; ++i) (void)hipEventDestroy(ev[i]);
   return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Solve without allocation (pasd_solve_static).  The whole solver state of one
+// solve (D, Y_n, the factors, the split-K partials of the GEMM-M reduction and
+// of the Gram, the control scalars and the problem descriptors) lives in one
+// file-scope device array of kStaticScratchBytes per GPU, which the code
+// object holds from load until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: its device address is resolved once per
+// device with hipGetSymbolAddress (with that device current) and kept in
+// g_scratch_dev.  Every call on a device reuses that device's array: the
+// state is cleared by a fill kernel at the start of each call, and calls that
+// overlap on one device race on it.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;  // 32 MiB per device
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each device, once resolved
+
+// Device address of `scratch` on device `dev` (the current device).
+int static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(PASD_ERR_UNSUPPORTED, "pasd_solve_static: device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PASD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return PASD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pasd_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+int pasd_solve_static(const pasd_config* cfg, const void* T, void* X, void* E, pasd_info* info) {
+  g_last_error.clear();
+  int rc = validate_impl(cfg);
+  if (rc != PASD_OK) return rc;
+  if (!T) return fail(PASD_ERR_INVALID_ARG, "T is NULL");
+  Plan pl;
+  make_plan(cfg, pl, /*own_T=*/false);  // T is read in place from the caller's buffer
+  if (pl.L.total > kStaticScratchBytes)
+    return fail(PASD_ERR_UNSUPPORTED, "pasd_solve_static: the solve needs " +
+                                          std::to_string(pl.L.total) + " bytes of state, above the " +
+                                          std::to_string(kStaticScratchBytes) + "-byte static scratch");
+  pasd_ctx ctx;  // host descriptor only; nothing of it is allocated
+  rc = ctx_init_host(&ctx, cfg, pl);
+  if (rc != PASD_OK) return rc;
+  ctx.graph_disabled = true;  // direct launches: instantiating a graph would allocate
+  DeviceGuard guard(ctx.dev);
+  void* base = nullptr;
+  rc = static_scratch(ctx.dev, &base);
+  if (rc != PASD_OK) return rc;
+  DevScalars host_sc;
+  ctx.host_sc = &host_sc;
+  ctx.bytes = pl.L.total;
+  rc = ctx_init_device(&ctx, pl, base, T, /*T_on_device=*/1, /*T_in_place=*/true);
+  const int status = rc == PASD_OK ? pasd_solve(&ctx, info) : rc;
+  if (status < 0) {
+    (void)hipStreamSynchronize(ctx.stream);
+    return status;
+  }
+  if (X || E) {
+    rc = pasd_get_result(&ctx, X, E, /*on_device=*/1);
+    if (rc != PASD_OK) return rc;
+  }
+  return status;
 }
 
 void pasd_destroy(pasd_ctx* ctx) {

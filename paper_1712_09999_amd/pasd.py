@@ -109,6 +109,8 @@ def lib():
             "pasd_profile": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_double),
                                             P(ctypes.c_int)]),
             "pasd_query_batch": (ctypes.c_int, [P(vp), ctypes.c_int, P(Info)]),
+            "pasd_solve_static": (ctypes.c_int, [P(Config), vp, vp, vp, P(Info)]),
+            "pasd_static_scratch_bytes": (ctypes.c_size_t, []),
             "pasd_destroy": (None, [vp]),
             "pasd_last_error": (ctypes.c_char_p, []),
         }
@@ -306,6 +308,29 @@ class Solver:
             if f"F{n}" in st:
                 self.import_(Q_FAC, n, st[f"F{n}"])
         self.import_(Q_SCALARS, 0, st["scalars"])
+
+
+def solve_static(T, ranks: Sequence[int], X=None, E=None, **kw):
+    """One solve through pasd_solve_static (no device allocation inside the
+    library): T, X and E are torch CUDA tensors of the state dtype, X and E
+    preallocated by the caller (either may be None).  Keyword arguments are
+    those of make_config.  Returns (status, Info)."""
+    import torch
+    cfg = make_config(tuple(int(d) for d in T.shape), ranks, device=T.device.index, **kw)
+    sdt = torch.float64 if cfg.precision == FP64 else torch.float32
+    for t in (T, X, E):
+        if t is not None and (t.dtype != sdt or not t.is_contiguous() or not t.is_cuda
+                              or tuple(t.shape) != tuple(T.shape)):
+            raise ValueError("T, X and E must be contiguous CUDA tensors of the state dtype and shape")
+    info = Info()
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None  # noqa: E731
+    code = lib().pasd_solve_static(ctypes.byref(cfg), ptr(T), ptr(X), ptr(E), ctypes.byref(info))
+    _check(code, allow=(OK, NOT_CONVERGED, PRECISION_FLOOR))
+    return code, info
+
+
+def static_scratch_bytes() -> int:
+    return int(lib().pasd_static_scratch_bytes())
 
 
 def step_batch(solvers: List[Solver], n_iters: int):
