@@ -385,6 +385,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--cpu-iters-1t", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32 and split-BF16 iteration rates of the headline workload")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--srv-requests", type=int, default=512)
@@ -396,6 +398,11 @@ def main():
     ap.add_argument("--phase-trials", type=int, default=1)
     ap.add_argument("--no-mri", action="store_true")
     ap.add_argument("--no-wide", action="store_true")
+    ap.add_argument("--workload", default="c4", choices=("c4", "c2", "c3", "c1"),
+                    help="configuration of the timed iterations (default c4, the headline; "
+                         "the others serve kernel traces and counter runs)")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32", "bf16"),
+                    help="precision of the timed iterations (default fp64)")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (3 times), the "
                          "reference kernel that scales hardware traffic counters to bytes")
@@ -416,19 +423,22 @@ def main():
 
     # ---- headline: 64^4, R_n = 6, FP64, timed iterations (no early stop) ----
     wl4 = workloads.make_config("c4")
-    dims, ranks = wl4.dims, wl4.ranks
-    T32 = wl4.observed(np.float32)
+    wlh = wl4 if args.workload == "c4" else workloads.make_config(args.workload)
+    dims, ranks = wlh.dims, wlh.ranks
+    T32 = wlh.observed(np.float32)
     T64 = T32.astype(np.float64)
-    ms_per_step, kernels = _timed_iterations(T64, ranks, "fp64", args.steps, args.warmup)
+    hprec = args.precision
+    ms_per_step, kernels = _timed_iterations(T64 if hprec == "fp64" else T32, ranks, hprec,
+                                             args.steps, args.warmup)
     value = 1000.0 / ms_per_step
-    _progress(f"64^4 FP64: timed {args.steps} iterations: {ms_per_step:.4f} ms each")
-    kb = kernel_bytes(dims, ranks, 8)
+    _progress(f"{args.workload} {hprec}: timed {args.steps} iterations: {ms_per_step:.4f} ms each")
+    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4)
     for k, b in kb.items():
         kernels[k]["alg_bytes"] = b
         kernels[k]["GB/s"] = b / (kernels[k]["ms"] * 1e-3) / 1e9
     dom = max(kb, key=lambda k: kernels[k]["ms"])
     ach = kernels[dom]["GB/s"]
-    traffic = _measured_traffic(dom)
+    traffic = _measured_traffic(dom) if (args.workload, hprec) == ("c4", "fp64") else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": kb[dom], "ms_per_launch": kernels[dom]["ms"]}
@@ -446,12 +456,14 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "ADMM iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "f32"}[hprec],
         "data": "synthetic",
-        "config": {"workload": "64x64x64x64 Tucker core 6^4 N(0,1) with orthonormal factors, "
-                               "min-max normalised to [0,1], 15% of entries replaced by 0 or 1; "
-                               "R_n=6, FP64 state, GEMMs, QR, eig and norms",
-                   "dims": list(dims), "ranks": list(ranks), "tol": wl4.tol},
+        "config": {"workload": ("64x64x64x64 Tucker core 6^4 N(0,1) with orthonormal factors, "
+                                "min-max normalised to [0,1], 15% of entries replaced by 0 or 1; "
+                                "R_n=6, FP64 state, GEMMs, QR, eig and norms")
+                   if (args.workload, hprec) == ("c4", "fp64") else f"{args.workload} {hprec}",
+                   "dims": list(dims), "ranks": list(ranks), "tol": wlh.tol},
         "roofline": roofline,
         "kernel_sum_ms": round(ksum, 5),
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
@@ -459,12 +471,13 @@ def main():
     }
 
     # mixed precision on the same workload: FP32 state and GEMMs, FP64 QR/eig/norms
-    ms32, k32 = _timed_iterations(T32, ranks, "fp32", args.steps, args.warmup)
-    ms16, _ = _timed_iterations(T32, ranks, "bf16", args.steps, args.warmup)
-    out["mixed"] = {"fp32": {"ms_per_step": round(ms32, 5), "iters_per_s": round(1e3 / ms32, 1),
-                             "kernels_ms": {k: round(v["ms"], 4) for k, v in k32.items()}},
-                    "bf16": {"ms_per_step": round(ms16, 5), "iters_per_s": round(1e3 / ms16, 1)}}
-    _progress(f"64^4 FP32: {ms32:.4f} ms/iteration; split-BF16 GEMMs: {ms16:.4f}")
+    if not args.no_mixed and args.workload == "c4":
+        ms32, k32 = _timed_iterations(T32, ranks, "fp32", args.steps, args.warmup)
+        ms16, _ = _timed_iterations(T32, ranks, "bf16", args.steps, args.warmup)
+        out["mixed"] = {"fp32": {"ms_per_step": round(ms32, 5), "iters_per_s": round(1e3 / ms32, 1),
+                                 "kernels_ms": {k: round(v["ms"], 4) for k, v in k32.items()}},
+                        "bf16": {"ms_per_step": round(ms16, 5), "iters_per_s": round(1e3 / ms16, 1)}}
+        _progress(f"64^4 FP32: {ms32:.4f} ms/iteration; split-BF16 GEMMs: {ms16:.4f}")
 
     # ---- full solves: every configuration, each precision against FP64 ------
     if not args.no_solve:

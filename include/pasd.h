@@ -208,6 +208,23 @@ int pasd_import(pasd_ctx *ctx, int quantity, int index, const void *src, int src
  * must be distinct and on the same device.  Asynchronous. */
 int pasd_step_batch(pasd_ctx *const *ctxs, int count, int n_iters);
 
+/* A captured batched step (serving): pasd_batch_create records n_iters
+ * iterations of every context of the list, grouped exactly as
+ * pasd_step_batch groups them, into one HIP graph (captured on a private
+ * stream; nothing runs during the call); pasd_batch_step replays it on the
+ * contexts' common stream (asynchronous), advancing each context that is
+ * still running by n_iters iterations with the same results, bitwise, as
+ * pasd_step_batch.  The graph holds the contexts' device state: every context
+ * must stay alive, unchanged in membership, until pasd_batch_destroy, and a
+ * context that has finished (converged, max_iter, floor) is skipped on the
+ * device.  A serving loop re-creates the batch when its resident set changes.
+ * Errors: PASD_ERR_INVALID_ARG for the lists pasd_step_batch rejects or an
+ * empty list; PASD_ERR_HIP if capture or instantiation fails (*out NULL). */
+typedef struct pasd_batch pasd_batch;
+int pasd_batch_create(pasd_ctx *const *ctxs, int count, int n_iters, pasd_batch **out);
+int pasd_batch_step(pasd_batch *batch);
+void pasd_batch_destroy(pasd_batch *batch);   /* NULL-safe */
+
 /* Kernels of one iteration, in launch order (indices of pasd_profile). */
 enum pasd_kernel {
   PASD_K_GEMM_M = 0,  /* M_n = G_n P_n^T split-K partials (eq. (10) operand) */

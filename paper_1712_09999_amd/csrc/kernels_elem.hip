@@ -292,7 +292,7 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
 // exact, Y_n + mu (D - Z_n) is one fused multiply-add), so wider registers would
 // change the stored iterate only through the rounding of mu.  The residual is
 // taken from the stored D.
-template <typename S, int NN, int VEC, int RP, typename IT>
+template <typename S, int NN, int VEC, int RP, typename IT, bool SPLIT1>
 __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk, bool xcd_split) {
   // Accumulation type of Z_n and type of the elementwise arithmetic.  Both are
   // the state type: wider registers were measured to leave FP32 convergence
@@ -311,16 +311,29 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   // one contiguous eighth of the tensor: the P_n columns a region needs are
   // fetched into one XCD's L2 instead of all eight, and each XCD's accesses
   // stay in one compact front.
+  // With SPLIT1 (32-bit offsets only) XCD x enumerates e over the segments
+  // of its mode-1 eighth: chunk = (e / f_seg) f_cp0 + x f_seg + e mod f_seg.
   IT c0 = 0, c1 = v.nchunk, first = (IT)lblk * blockDim.x, step = (IT)nblk * blockDim.x;
+  IT seg_base = 0;
   if (xcd_split) {
-    const IT per = (v.nchunk + kXcds - 1) / kXcds;
     const int x = lblk % kXcds;
-    c0 = (IT)x * per;
-    c1 = c0 + per < v.nchunk ? c0 + per : v.nchunk;
     first = (IT)(lblk / kXcds) * blockDim.x;
     step = (IT)(nblk / kXcds) * blockDim.x;
+    if constexpr (SPLIT1) {
+      c1 = v.nchunk / kXcds;  // every XCD enumerates an equal share
+      seg_base = (IT)x * (IT)pb.f_seg;
+    } else {
+      const IT per = (v.nchunk + kXcds - 1) / kXcds;
+      c0 = (IT)x * per;
+      c1 = c0 + per < v.nchunk ? c0 + per : v.nchunk;
+    }
   }
-  for (IT c = c0 + first + threadIdx.x; c < c1; c += step) {
+  for (IT e = c0 + first + threadIdx.x; e < c1; e += step) {
+    IT c = e;
+    if constexpr (SPLIT1) {
+      const IT sg = (IT)fastdiv((uint32_t)e, pb.fd_seg);
+      c = sg * (IT)pb.f_cp0 + seg_base + (e - sg * (IT)pb.f_seg);
+    }
     const IT row = div_fixed<IT>(c, v.Q, v.fq);
     const IT i = (c - row * v.Q) * VEC;
     const IT x0 = c * VEC;
@@ -328,11 +341,13 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     gload<S, VEC, IT>(v.T, x0, tv);
     ZT z[NN][VEC];
     S y[NN][VEC];
+    // the streamed operands first: the first mode's wait then covers their
+    // HBM round trip and every later mode waits only for its own (cached)
+    // factor loads
 #pragma unroll
-    for (int n = 0; n < NN; ++n) {
-      recon_row<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n]);
-      gload<S, VEC, IT>(v.Y[n], x0, y[n]);
-    }
+    for (int n = 0; n < NN; ++n) gload<S, VEC, IT>(v.Y[n], x0, y[n]);
+#pragma unroll
+    for (int n = 0; n < NN; ++n) recon_row<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n]);
     S dv[VEC];
 #pragma unroll
     for (int t = 0; t < VEC; ++t) {
@@ -364,7 +379,7 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
 
 // The fused pass over a batch; each problem takes the 16-byte vector path when
 // its last dimension is a multiple of the vector width.
-template <typename S, int NN, int RP, typename IT>
+template <typename S, int NN, int RP, typename IT, bool SPLIT1>
 __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
   const Problem<S>& pb = *bt.p[req];
@@ -373,10 +388,19 @@ __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
   const int nblk = bt.start[req + 1] - s0;
   const int lblk = blockIdx.x - s0;
   const bool xcd_split = nblk % kXcds == 0 && s0 % kXcds == 0;
-  if (pb.vecw)
-    fused_body<S, NN, VW<S>::n, RP, IT>(pb, lblk, nblk, xcd_split);
-  else
-    fused_body<S, NN, 1, RP, IT>(pb, lblk, nblk, xcd_split);
+  if constexpr (SPLIT1) {
+    // launched only for one problem with fsplit1 set and a grid of whole
+    // XCD rounds (a separate instantiation keeps the other's registers low)
+    if (pb.vecw)
+      fused_body<S, NN, VW<S>::n, RP, IT, true>(pb, lblk, nblk, true);
+    else
+      fused_body<S, NN, 1, RP, IT, true>(pb, lblk, nblk, true);
+  } else {
+    if (pb.vecw)
+      fused_body<S, NN, VW<S>::n, RP, IT, false>(pb, lblk, nblk, xcd_split);
+    else
+      fused_body<S, NN, 1, RP, IT, false>(pb, lblk, nblk, xcd_split);
+  }
 }
 
 // One wave: fold the residual slots (and clear them for the next iteration),
@@ -528,10 +552,17 @@ static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {
   const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.fused_blocks; });
   bool idx32 = true;
   for (int r = 0; r < ls.count; ++r) idx32 = idx32 && ls.host[r]->idx32;
-  if (idx32)
-    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t>), dim3(grid), dim3(256), 0, s, b);
+  // the mode-1 order over the XCDs (Problem::fsplit1) for a launch of one
+  // problem whose blocks fill whole XCD rounds; the traversal order changes
+  // no result
+  const bool split1 = idx32 && ls.count == 1 && ls.host[0]->fsplit1 && grid % kXcds == 0;
+  if (split1)
+    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, true>), dim3(grid), dim3(256), 0, s, b);
+  else if (idx32)
+    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, false>), dim3(grid), dim3(256), 0, s, b);
   else  // offsets beyond 32 bits: 64-bit indexing, full rank tile (or the tile loop)
-    hipLaunchKernelGGL((k_fused<S, NN, RP == 0 ? 0 : kRT, uint64_t>), dim3(grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL((k_fused<S, NN, RP == 0 ? 0 : kRT, uint64_t, false>), dim3(grid), dim3(256), 0,
+                       s, b);
 }
 
 // The rank loop is unrolled to the largest R_n of the set, rounded up to even

@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 
 constexpr int kMWaves = 8;
 
-template <typename S, bool BF, bool RS>
+template <typename S, bool BF, bool RS, bool NARROW>
 __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
   typedef typename MM<S>::vec_t V;
@@ -425,7 +425,9 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
         }
     }
   } else if (g.B > 1) {
-    constexpr int IBP = sizeof(S) == 4 ? 8 : 4;  // row blocks per pass (register budget)
+    // row blocks per pass (register budget); NARROW launches (every I_n <= 64)
+    // need at most 4
+    constexpr int IBP = (sizeof(S) == 4 && !NARROW) ? 8 : 4;
     const int64_t nsteps = (g.J + 15) / 16;
     const int64_t per_blk = (nsteps + mb.mblocks - 1) / mb.mblocks;
     const int64_t sbeg = (int64_t)blk * per_blk;
@@ -529,7 +531,8 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
     }
   } else {
     // rows a, K-step of 4 rows
-    constexpr int CHP = sizeof(S) == 4 ? 4 : 2;  // 64-wide i chunks per pass
+    // 64-wide i chunks per pass; NARROW launches (every I_n <= 64) need one
+    constexpr int CHP = NARROW ? 1 : (sizeof(S) == 4 ? 4 : 2);
     const int64_t nsteps = (g.A + 3) / 4;
     const int64_t per_blk = (nsteps + mb.mblocks - 1) / mb.mblocks;
     const int64_t sbeg = (int64_t)blk * per_blk;
@@ -845,7 +848,10 @@ int gemm_m_blocks(const ModeGeom& g, int N) {
   // one block of 8 waves per compute unit across the N modes of a solve (a
   // block holds its CU's register file), capped by the available K-steps
   const int64_t steps = g.B > 1 ? (g.J + 15) / 16 : (g.A + 3) / 4;
-  const int64_t want = std::max(16, kCUs / std::max(1, N));
+  // modes of at most 64 rows: four blocks per compute unit (one block's
+  // waves hold too few loads in flight when each step covers only 4 row
+  // blocks; measured at 64^4)
+  const int64_t want = std::max(16, (g.I <= 64 ? 4 : 1) * kCUs / std::max(1, N));
   const int64_t maxb = (steps + kMWaves - 1) / kMWaves;
   return (int)std::max<int64_t>(1, std::min(want, maxb));
 }
@@ -922,19 +928,27 @@ static void launch_gemm_m_set(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_M); });
   const bool one = ls.count == 1;
+  // every mode of every problem at most 64 rows: the narrow instantiation
+  bool narrow = true;
+  for (int r = 0; r < ls.count; ++r)
+    for (int n = 0; n < ls.host[r]->N; ++n) narrow = narrow && ls.host[r]->g[n].I <= 64;
   if constexpr (sizeof(S) == 4) {
     if (bf16_set(ls)) {
-      if (one)
-        hipLaunchKernelGGL((k_gemm_m<S, true, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+      if (narrow)
+        hipLaunchKernelGGL((k_gemm_m<S, true, false, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+      else if (one)
+        hipLaunchKernelGGL((k_gemm_m<S, true, true, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
       else
-        hipLaunchKernelGGL((k_gemm_m<S, true, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+        hipLaunchKernelGGL((k_gemm_m<S, true, false, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
       return;
     }
   }
-  if (one)
-    hipLaunchKernelGGL((k_gemm_m<S, false, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+  if (narrow)
+    hipLaunchKernelGGL((k_gemm_m<S, false, false, true>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+  else if (one)
+    hipLaunchKernelGGL((k_gemm_m<S, false, true, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
   else
-    hipLaunchKernelGGL((k_gemm_m<S, false, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
+    hipLaunchKernelGGL((k_gemm_m<S, false, false, false>), dim3(tot), dim3(64 * kMWaves), 0, s, b);
 }
 
 template <typename S>

@@ -109,6 +109,16 @@ struct Problem {
   int fused_blocks;  // blocks of the fused pass for this problem
   int vecw;          // last dimension divisible by the 16-byte vector width (fused pass)
   int idx32;         // every element offset of the fused pass fits 32-bit byte offsets
+  // Order of the fused pass over the 8 XCDs.  0: XCD x sweeps the x-th
+  // contiguous eighth of the tensor.  1 (chosen when P_0 is too large to stay
+  // in one XCD's L2, N >= 3, I_1 divisible by 8, 32-bit offsets): XCD x
+  // sweeps, for every mode-0 index in turn, the x-th eighth of the mode-1
+  // range, so that it only needs the eighth of P_0's columns with i_1 in that
+  // range.  In chunks of the pass: f_cp0 per mode-0 slab, f_cp1 per mode-1
+  // slab, f_seg = f_cp1 I_1 / 8 per segment (one mode-0 index, one XCD).
+  int fsplit1;
+  uint32_t f_cp0, f_cp1, f_seg;
+  FastDiv fd_seg;
   // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
   // the rows per mode-n fibre index (B_n / I_N) and I_n
   FastDiv fd_q;

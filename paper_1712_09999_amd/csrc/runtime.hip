@@ -235,6 +235,15 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   p.idx32 = span * (int64_t)sizeof(S) < (int64_t(1) << 31) ? 1 : 0;
   const int64_t IN = p.g[ctx->N - 1].I;
   p.fd_q = make_fastdiv((uint32_t)(p.idx32 ? IN / (p.vecw ? vw : 1) : 1));
+  // Mode-1 order of the fused pass when P_0 would not stay in one XCD's L2
+  // (4 MB, shared with the streamed tensors): more than 2 MiB of P_0.
+  const int64_t vec = p.vecw ? vw : 1;
+  const int64_t p0_bytes = (int64_t)p.g[0].R * p.g[0].J * (int64_t)sizeof(S);
+  p.fsplit1 = (ctx->N >= 3 && p.idx32 && p.g[1].I % kXcds == 0 && p0_bytes > (int64_t(2) << 20)) ? 1 : 0;
+  p.f_cp1 = p.fsplit1 ? (uint32_t)(p.g[1].B / vec) : 1;
+  p.f_cp0 = p.fsplit1 ? (uint32_t)(p.g[0].B / vec) : 1;
+  p.f_seg = p.fsplit1 ? p.f_cp1 * (uint32_t)(p.g[1].I / kXcds) : 1;
+  p.fd_seg = make_fastdiv(p.f_seg);
   for (int n = 0; n < kMaxN; ++n) {
     const bool inner = n < ctx->N - 1 && p.idx32;
     p.fd_rb[n] = make_fastdiv((uint32_t)(inner ? p.g[n].B / IN : 1));
@@ -869,8 +878,11 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
   }
 }
 
-int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
-  g_last_error.clear();
+}  // extern "C"
+
+namespace {
+
+int check_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
   if (count < 0 || (count > 0 && !ctxs)) return fail(PASD_ERR_INVALID_ARG, "bad context list");
   for (int i = 0; i < count; ++i) {
     if (!ctxs[i]) return fail(PASD_ERR_INVALID_ARG, "NULL context in batch");
@@ -881,10 +893,13 @@ int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
       return fail(PASD_ERR_INVALID_ARG, "contexts of a batch must share one stream");
   }
   if (n_iters < 0) return fail(PASD_ERR_INVALID_ARG, "n_iters must be >= 0");
-  if (count == 0 || n_iters == 0) return PASD_OK;
-  DeviceGuard guard(ctxs[0]->dev);
-  // Group by (precision, order); every group runs the eight kernels of an
-  // iteration as grouped launches over up to kMaxBatch problems.
+  return PASD_OK;
+}
+
+// Enqueue n_iters iterations of every context on `s`: contexts are grouped by
+// (precision, order) and every group runs the kernels of an iteration as
+// grouped launches over up to kMaxBatch problems.
+void enqueue_batch(pasd_ctx* const* ctxs, int count, int n_iters, hipStream_t s) {
   std::vector<char> taken(count, 0);
   for (int i = 0; i < count; ++i) {
     if (taken[i]) continue;
@@ -904,7 +919,7 @@ int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
           ls.host[r] = &grp[c0 + r]->pd;
           ls.dev[r] = static_cast<const Problem<double>*>(grp[c0 + r]->dev_prob);
         }
-        enqueue_iterations<double>(ls, n_iters, ctxs[0]->stream, nullptr);
+        enqueue_iterations<double>(ls, n_iters, s, nullptr);
       } else {
         LaunchSet<float> ls;
         ls.count = cnt;
@@ -912,11 +927,85 @@ int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
           ls.host[r] = &grp[c0 + r]->pf;
           ls.dev[r] = static_cast<const Problem<float>*>(grp[c0 + r]->dev_prob);
         }
-        enqueue_iterations<float>(ls, n_iters, ctxs[0]->stream, nullptr);
+        enqueue_iterations<float>(ls, n_iters, s, nullptr);
       }
     }
   }
+}
+
+}  // namespace
+
+// A captured batched step: n_iters iterations of a fixed set of contexts,
+// replayed as one graph on the contexts' stream.
+struct pasd_batch {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
+  g_last_error.clear();
+  int rc = check_batch(ctxs, count, n_iters);
+  if (rc != PASD_OK) return rc;
+  if (count == 0 || n_iters == 0) return PASD_OK;
+  DeviceGuard guard(ctxs[0]->dev);
+  enqueue_batch(ctxs, count, n_iters, ctxs[0]->stream);
   HIP_TRY(hipGetLastError());
+  return PASD_OK;
+}
+
+void pasd_batch_destroy(pasd_batch* b) {
+  if (!b) return;
+  {
+    DeviceGuard guard(b->dev);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  }
+  delete b;
+}
+
+int pasd_batch_create(pasd_ctx* const* ctxs, int count, int n_iters, pasd_batch** out) {
+  g_last_error.clear();
+  if (!out) return fail(PASD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_batch(ctxs, count, n_iters);
+  if (rc != PASD_OK) return rc;
+  if (count == 0 || n_iters < 1) return fail(PASD_ERR_INVALID_ARG, "empty batch");
+  DeviceGuard guard(ctxs[0]->dev);
+  pasd_batch* b = new pasd_batch();
+  b->dev = ctxs[0]->dev;
+  b->stream = ctxs[0]->stream;
+  hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    b->cap_stream = nullptr;
+    pasd_batch_destroy(b);
+    return fail(PASD_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+  }
+  e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  hipGraph_t g = nullptr;
+  if (e == hipSuccess) {
+    enqueue_batch(ctxs, count, n_iters, b->cap_stream);
+    e = hipStreamEndCapture(b->cap_stream, &g);
+  }
+  if (e == hipSuccess && g) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (e != hipSuccess || !b->exec) {
+    (void)hipGetLastError();
+    pasd_batch_destroy(b);
+    return fail(PASD_ERR_HIP, std::string("capturing the batched step: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return PASD_OK;
+}
+
+int pasd_batch_step(pasd_batch* b) {
+  g_last_error.clear();
+  if (!b || !b->exec) return fail(PASD_ERR_INVALID_ARG, "batch is NULL");
+  DeviceGuard guard(b->dev);
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   return PASD_OK;
 }
 

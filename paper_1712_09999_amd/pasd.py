@@ -109,6 +109,9 @@ def lib():
             "pasd_profile": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_double),
                                             P(ctypes.c_int)]),
             "pasd_query_batch": (ctypes.c_int, [P(vp), ctypes.c_int, P(Info)]),
+            "pasd_batch_create": (ctypes.c_int, [P(vp), ctypes.c_int, ctypes.c_int, P(vp)]),
+            "pasd_batch_step": (ctypes.c_int, [vp]),
+            "pasd_batch_destroy": (None, [vp]),
             "pasd_solve_static": (ctypes.c_int, [P(Config), vp, vp, vp, P(Info)]),
             "pasd_static_scratch_bytes": (ctypes.c_size_t, []),
             "pasd_destroy": (None, [vp]),
@@ -337,6 +340,35 @@ def step_batch(solvers: List[Solver], n_iters: int):
     """n_iters iterations of every solver as grouped launches (pasd_step_batch)."""
     arr = (ctypes.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
     _check(lib().pasd_step_batch(arr, len(solvers), int(n_iters)))
+
+
+class BatchGraph:
+    """n_iters iterations of a fixed list of solvers captured once as a HIP
+    graph (pasd_batch_create) and replayed by step() (pasd_batch_step).  The
+    solvers must stay open while the graph exists."""
+
+    def __init__(self, solvers: List[Solver], n_iters: int):
+        arr = (ctypes.c_void_p * len(solvers))(*[s.handle.value for s in solvers])
+        h = ctypes.c_void_p()
+        _check(lib().pasd_batch_create(arr, len(solvers), int(n_iters), ctypes.byref(h)))
+        self._h = h
+        self.solvers = list(solvers)
+
+    def step(self):
+        if self._h is None:
+            raise PasdError(ERR_STATE, "batch graph destroyed")
+        _check(lib().pasd_batch_step(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pasd_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def query_batch(solvers: List[Solver]) -> List[Info]:

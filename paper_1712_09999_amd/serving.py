@@ -4,8 +4,11 @@ Requests (one TRPCA solve each) arrive over time.  The loop admits arrived
 requests while a slot is free and their device footprint (pasd_footprint)
 fits the HBM budget, keeps every admitted solve resident on the GPU, and
 advances all of them together: each step is `step_iters` iterations of every
-resident solve as grouped kernel launches (pasd_step_batch), followed by one
-batched status read (pasd_query_batch).  Solves that converged or hit their
+resident solve as grouped kernel launches, replayed from a HIP graph captured
+for the current resident set (pasd_batch_create / pasd_batch_step; captured
+again whenever a solve is admitted or retired) or, with graphs=False,
+launched directly (pasd_step_batch), followed by one batched status read
+(pasd_query_batch).  Solves that converged or hit their
 iteration cap are retired (results copied out, device memory released) and
 their slots go to waiting requests.  A request's latency is its completion
 time minus its arrival time, queueing included.
@@ -58,9 +61,10 @@ class Result:
 class Server:
     def __init__(self, precision: str = "fp32", max_slots: int = 64,
                  hbm_budget: Optional[int] = None, step_iters: int = 4, device: int = 0,
-                 keep_results: bool = True):
+                 keep_results: bool = True, graphs: bool = True):
         import torch
         self.precision = precision
+        self.graphs = bool(graphs)
         self.max_slots = int(max_slots)
         self.step_iters = int(step_iters)
         self.device = device
@@ -86,6 +90,9 @@ class Server:
         results: List[Result] = []
         used = 0
         steps = 0
+        captures = 0
+        graph = None  # BatchGraph of the current resident set
+        graph_set: tuple = ()
         t0 = time.perf_counter()
         while pending or active:
             now = time.perf_counter() - t0
@@ -107,8 +114,19 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 continue
-            P.step_batch([a[1] for a in active], self.step_iters)
-            infos = P.query_batch([a[1] for a in active])
+            solvers = [a[1] for a in active]
+            if self.graphs:
+                key = tuple(id(x) for x in solvers)
+                if graph is None or key != graph_set:
+                    if graph is not None:
+                        graph.close()
+                    graph = P.BatchGraph(solvers, self.step_iters)
+                    graph_set = key
+                    captures += 1
+                graph.step()
+            else:
+                P.step_batch(solvers, self.step_iters)
+            infos = P.query_batch(solvers)
             steps += 1
             keep = []
             for (req, s, fp, adm), info in zip(active, infos):
@@ -119,13 +137,18 @@ class Server:
                     done_t = time.perf_counter() - t0
                     results.append(Result(req.rid, req.arrival if realtime else 0.0, adm, done_t,
                                           info.iterations, bool(info.converged), info.done, X, E))
+                    if graph is not None:  # the graph holds this solve's state
+                        graph.close()
+                        graph = None
                     s.close()
                     used -= fp
                 else:
                     keep.append((req, s, fp, adm))
             active = keep
+        if graph is not None:
+            graph.close()
         torch.cuda.synchronize()
-        self.stats = {"steps": steps, "wall_s": time.perf_counter() - t0}
+        self.stats = {"steps": steps, "captures": captures, "wall_s": time.perf_counter() - t0}
         return sorted(results, key=lambda r: r.rid)
 
 

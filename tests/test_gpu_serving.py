@@ -65,6 +65,35 @@ def test_batched_steps_equal_alone(precision):
             np.testing.assert_array_equal(a.export(P.Q_Y, n), b.export(P.Q_Y, n))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_graph_replays_equal_direct_batches(precision):
+    """pasd_batch_step replays a captured graph of the grouped step: after
+    every replay (with eager work and synchronisations between replays) the
+    iterates equal those of the same number of direct pasd_step_batch calls,
+    bitwise; a solve that finished meanwhile is skipped on the device."""
+    dt = np.float32 if precision == "fp32" else np.float64
+    wls = [_wl(*s) for s in SPECS]
+    mk = lambda wl, **kw: P.Solver(wl.observed(dt), wl.ranks, precision=precision, mu0=0.01,
+                                   **kw)
+    # the last solve stops at max_iter = 10, inside the second replay
+    direct = [mk(wl, tol=0.0, max_iter=10 ** 6) for wl in wls[:3]] + [mk(wls[3], tol=0.0, max_iter=10)]
+    graphed = [mk(wl, tol=0.0, max_iter=10 ** 6) for wl in wls[:3]] + [mk(wls[3], tol=0.0, max_iter=10)]
+    g = P.BatchGraph(graphed, 6)
+    for rep in range(4):
+        P.step_batch(direct, 6)
+        g.step()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # eager work between replays
+        for a, b in zip(direct, graphed):
+            ia, ib = a.query(), b.query()
+            assert ia.iterations == ib.iterations == min(6 * (rep + 1), a.cfg.max_iter)
+            np.testing.assert_array_equal(a.export(P.Q_D), b.export(P.Q_D))
+            np.testing.assert_array_equal(a.export(P.Q_Y, 1), b.export(P.Q_Y, 1))
+    g.close()
+    with pytest.raises(P.PasdError):
+        P.BatchGraph([], 4)
+
+
 def test_batch_groups_mixed_precision_and_order():
     wl3 = _wl(*SPECS[0])
     wl4 = workloads.tucker_workload("srv4", (10, 12, 8, 9), (2, 2, 2, 2), 0.1, 21,
