@@ -39,7 +39,7 @@ extern "C" {
 #endif
 
 #define PASD_MAX_ORDER 8   /* largest tensor order N supported */
-#define PASD_MAX_RANK 64   /* largest R_n supported; I_n R_n <= 8192 for R_n <= 16
+#define PASD_MAX_RANK 64   /* largest R_n supported; I_n R_n <= 2^20 for R_n <= 16
                               and I_n R_n <= 16384 above (QR workspace) */
 
 enum pasd_status {

@@ -303,12 +303,16 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
       for (int b = 0; b < w; ++b) part[b] += part[b + w];
     Sm[r][c] = part[0];
     W[r][c] = (warm && in) ? wev : (r == c ? 1.0 : 0.0);
+    // U_n is staged in LDS when it fits (a tall mode reads it from global
+    // memory below)
+    if (nU <= kQrLds) {
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int e = tid + 256 * u;
-      if (e < nU) Ul[e] = uv[u];
+      for (int u = 0; u < kU; ++u) {
+        const int e = tid + 256 * u;
+        if (e < nU) Ul[e] = uv[u];
+      }
+      for (int e = tid + 256 * kU; e < nU; e += 256) Ul[e] = mb.U[e];
     }
-    for (int e = tid + 256 * kU; e < I * R; e += 256) Ul[e] = mb.U[e];
   }
   __syncthreads();
   {  // T1 = S W0 with the upper triangle of S mirrored
@@ -456,6 +460,7 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
     double wfb[kRT / 4];
 #pragma unroll
     for (int st = 0; st < kRT / 4; ++st) wfb[st] = T1[4 * st + q][p];
+    const bool ul = I * R <= kQrLds;
     for (int rb = wave; rb < nrb; rb += 4) {
       const int row = 16 * rb + p;
       const int rc = row < I ? row : I - 1;
@@ -463,7 +468,8 @@ __global__ void __launch_bounds__(256) k_eig(Batch<S> bt) {
 #pragma unroll
       for (int st = 0; st < kRT / 4; ++st) {
         const int k = 4 * st + q;
-        const double av = Ul[rc * R + (k < R ? k : 0)];
+        const int e = rc * R + (k < R ? k : 0);
+        const double av = ul ? Ul[e] : mb.U[e];
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64((row < I && k < R) ? av : 0.0, wfb[st], acc, 0, 0, 0);
       }
 #pragma unroll
@@ -904,6 +910,240 @@ static bool qr_reg_rp(const Batch<S>& b, int grid, int rmax, hipStream_t s) {
     hipLaunchKernelGGL((k_qr_reg<S, (TR > 4 ? 4 : TR), 16>), dim3(grid), dim3(64), 0, s, b);
   }
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// QR of a tall M_n (R_n <= 16 and I_n R_n above the 8192 doubles the LDS and
+// register variants hold), one block of kTallThreads per (problem, mode),
+// with A in global memory: M_n's own buffer (rows of kRT doubles, columns
+// >= R_n zero), overwritten.  CholeskyQR2 as in k_qr_chol: the Gram on the
+// FP64 matrix cores (each wave four rows per MFMA, the wave partials summed in
+// LDS in a fixed order), the Cholesky factor and R^-1 by one wave in LDS
+// (lane c owns column c), then A <- A R^-1 one row per thread.  A pass fails
+// when a pivot is below floor2 times its column's squared norm (1e-12, then
+// 1/2, as in k_qr_chol); then the Householder QR of the current A (M_n, or
+// the first pass's A R^-1, which still spans range(M_n)) runs on the whole
+// block: per column one block-wide batched reduction of the dot products
+// (per-wave sums in LDS, summed in wave order) and one update pass, the
+// LAPACK dgeqr2 / dorg2r conventions of qr_factor_col / qr_form_col.
+// ---------------------------------------------------------------------------
+constexpr int kTallThreads = 1024;
+constexpr int kTallWaves = kTallThreads / 64;
+
+// Sum part[0..K) over the block (per-wave shuffles, then the waves in order);
+// the sums land in out[0..K).  Ends with a barrier.
+template <int K>
+__device__ __forceinline__ void tall_block_sum(double (&part)[K], double (*red)[kRT + 1],
+                                               double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double v = wave_sum(part[j]);
+    if (lane == 0) red[w][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double t = 0.0;
+    for (int v = 0; v < kTallWaves; ++v) t += red[v][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kTallThreads) k_qr_tall(Batch<S> bt) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int n = blockIdx.x - bt.start[req];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int I = g.I, R = g.R, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  double* A = mb.M;
+  __shared__ double Cp[kTallWaves][kRT * kRT];  // per-wave Gram partials
+  __shared__ double C[kRT][kRT + 1];            // the Gram, then R (upper triangle)
+  __shared__ double X[kRT][kRT + 1];            // R^-1
+  __shared__ double red[kTallWaves][kRT + 1];
+  __shared__ double bc[2 * kRT];                // reduced sums, then row c of A
+  __shared__ double tauv[kRT];
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    // C = A^T A: lane (p, q) supplies A[4 st + q][p] to both operands
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    const int nst = (I + 3) / 4;
+    constexpr int U = 8;
+    for (int s0 = w; s0 < nst; s0 += kTallWaves * U) {
+      double a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = 4 * (s0 + kTallWaves * u) + q;
+        a[u] = A[(int64_t)(i < I ? i : I - 1) * kRT + p];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = 4 * (s0 + kTallWaves * u) + q;
+        const double x = (i < I && p < R) ? a[u] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Cp[w][(4 * v + q) * kRT + p] = acc[v];
+    __syncthreads();
+    if (tid < kRT * kRT) {
+      double t = 0.0;
+      for (int v = 0; v < kTallWaves; ++v) t += Cp[v][tid];
+      C[tid / kRT][tid % kRT] = t;
+    }
+    __syncthreads();
+    if (w == 0) {
+      // right-looking Cholesky C = R^T R on the upper triangle, lane c owns
+      // column c; columns >= R get r_cc = 1
+      const double floor2 = pass == 0 ? 1e-12 : 0.5;
+      const double cdiag = lane < kRT ? C[lane][lane] : 0.0;
+      bool good = true;
+      for (int j = 0; j < kRT; ++j) {
+        // pivot d (row j already reduced by the earlier steps), row j of R,
+        // then the rank-one update of the trailing columns, each lane its own
+        const double d = C[j][j];
+        const bool real = j < R;
+        good = good && (!real || d > floor2 * __shfl(cdiag, j, 64));
+        const double hj = (real && d > 0.0) ? rsqrt_nr(d) : 1.0;
+        const double rjj = (real && d > 0.0) ? d * hj : 1.0;
+        const bool mine = lane > j && lane < kRT;
+        const double rjl = mine && real ? C[j][lane] * hj : 0.0;
+        qr_sync<false>();
+        if (mine) C[j][lane] = rjl;
+        if (lane == j) C[j][j] = rjj;
+        qr_sync<false>();
+        if (mine)
+          for (int k = j + 1; k <= lane; ++k) C[k][lane] = fma(-C[j][k], rjl, C[k][lane]);
+        qr_sync<false>();
+      }
+      good = __builtin_amdgcn_readfirstlane(good ? 1 : 0) != 0;
+      if (!good && lane == 0) bad = 1;
+      // X = R^-1, column `lane` by back substitution
+      if (lane < kRT) {
+        double x[kRT];
+#pragma unroll
+        for (int i = kRT - 1; i >= 0; --i) {
+          double t = i == lane ? 1.0 : 0.0;
+#pragma unroll
+          for (int k = i + 1; k < kRT; ++k) t = fma(-C[i][k], x[k], t);
+          x[i] = i <= lane ? t / C[i][i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kRT; ++i) X[i][lane] = x[i];
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    // A <- A X, one row per thread
+    for (int i = tid; i < I; i += kTallThreads) {
+      double a[kRT];
+      const double* row = A + (int64_t)i * kRT;
+#pragma unroll
+      for (int c = 0; c < kRT; c += 2) {
+        const d2v v = *reinterpret_cast<const d2v*>(row + c);
+        a[c] = c < R ? v[0] : 0.0;
+        a[c + 1] = c + 1 < R ? v[1] : 0.0;
+      }
+      double o[kRT];
+#pragma unroll
+      for (int c = 0; c < kRT; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k <= c; ++k) t = fma(a[k], X[k][c], t);
+        o[c] = c < R ? t : 0.0;
+      }
+      if (pass == 0) {
+#pragma unroll
+        for (int c = 0; c < kRT; ++c) A[(int64_t)i * kRT + c] = o[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < kRT; ++c) {
+          if (c < R) mb.U[(int64_t)i * R + c] = o[c];
+          mb.Us[(int64_t)i * kRT + c] = (S)o[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!bad) return;
+  // Householder QR of A (column-wise, rows of A owned by threads i = tid + kTallThreads k)
+  for (int c = 0; c < R; ++c) {
+    double part[kRT];
+#pragma unroll
+    for (int j = 0; j < kRT; ++j) part[j] = 0.0;
+    for (int i = c + 1 + tid; i < I; i += kTallThreads) {
+      const double* row = A + (int64_t)i * kRT;
+      const double ac = row[c];
+#pragma unroll
+      for (int j = 0; j < kRT; ++j) part[j] = fma(ac, j >= c && j < R ? row[j] : 0.0, part[j]);
+    }
+    if (tid == 0) {
+#pragma unroll
+      for (int j = 0; j < kRT; ++j) bc[kRT + j] = A[(int64_t)c * kRT + j];
+    }
+    tall_block_sum<kRT>(part, red, bc);
+    // d_j = bc[j] (j >= c; d_c is the squared norm below the diagonal),
+    // row c of A in bc[kRT + j]
+    const double xnorm2 = bc[c], alpha = bc[kRT + c];
+    double tc = 0.0, beta = alpha, scale = 0.0;
+    if (xnorm2 > 0.0) {
+      const double n2 = fma(alpha, alpha, xnorm2);
+      beta = -copysign(n2 * rsqrt_nr(n2), alpha);
+      tc = (beta - alpha) * rcp_nr(beta);
+      scale = rcp_nr(alpha - beta);
+    }
+    for (int i = c + tid; i < I; i += kTallThreads) {
+      double* row = A + (int64_t)i * kRT;
+      const double v = i > c ? row[c] * scale : 1.0;
+      for (int j = c + 1; j < R; ++j) row[j] -= tc * (bc[kRT + j] + scale * bc[j]) * v;
+      row[c] = i > c ? v : beta;
+    }
+    if (tid == 0) tauv[c] = tc;
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{R-1} [I_R; 0], columns R-1 down to 0
+  for (int c = R - 1; c >= 0; --c) {
+    const double tc = tauv[c];
+    double part[kRT];
+#pragma unroll
+    for (int j = 0; j < kRT; ++j) part[j] = 0.0;
+    for (int i = c + 1 + tid; i < I; i += kTallThreads) {
+      const double* row = A + (int64_t)i * kRT;
+      const double v = row[c];
+#pragma unroll
+      for (int j = 0; j < kRT; ++j) part[j] = fma(v, j > c && j < R ? row[j] : 0.0, part[j]);
+    }
+    if (tid == 0) {
+#pragma unroll
+      for (int j = 0; j < kRT; ++j) bc[kRT + j] = A[(int64_t)c * kRT + j];
+    }
+    tall_block_sum<kRT>(part, red, bc);
+    for (int i = tid; i < I; i += kTallThreads) {
+      double* row = A + (int64_t)i * kRT;
+      if (i >= c) {
+        const double v = i > c ? row[c] : 1.0;
+        for (int j = c + 1; j < R; ++j) row[j] -= tc * (bc[kRT + j] + bc[j]) * v;
+      }
+      row[c] = i > c ? -tc * row[c] : (i == c ? 1.0 - tc : 0.0);
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < I; i += kTallThreads) {
+#pragma unroll
+    for (int c = 0; c < kRT; ++c) {
+      const double v = c < R ? A[(int64_t)i * kRT + c] : 0.0;
+      if (c < R) mb.U[(int64_t)i * R + c] = v;
+      mb.Us[(int64_t)i * kRT + c] = (S)v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1521,9 +1761,33 @@ __global__ void __launch_bounds__(kWideThreads) k_eig_w(Batch<S> bt) {
 // One wave per (problem, mode); the register variant is sized for the largest
 // I_n and R_n of the set, the LDS variant takes what does not fit.  With the
 // keep tie-break on any problem of the set, its transform of M_n runs first.
+// Problems with a tall mode (I_n R_n > kQrLds) take k_qr_tall for every mode.
 template <typename S>
-static void launch_qr_narrow(const LaunchSet<S>& ls, hipStream_t s) {
+static bool has_tall_mode(const Problem<S>& p) {
+  for (int n = 0; n < p.N; ++n)
+    if (p.g[n].I * p.g[n].R > kQrLds) return true;
+  return false;
+}
+
+template <typename S>
+static void launch_qr_narrow(const LaunchSet<S>& all, hipStream_t s) {
+  LaunchSet<S> ls, tall;
+  ls.count = tall.count = 0;
+  for (int r = 0; r < all.count; ++r) {
+    LaunchSet<S>& d = has_tall_mode(*all.host[r]) ? tall : ls;
+    d.host[d.count] = all.host[r];
+    d.dev[d.count] = all.dev[r];
+    ++d.count;
+  }
   Batch<S> b;
+  if (tall.count) {
+    const int grid = make_batch(tall, b, [](const Problem<S>& p) { return p.N; });
+    bool keep = false;
+    for (int r = 0; r < tall.count; ++r) keep = keep || tall.host[r]->tiebreak_keep;
+    if (keep) hipLaunchKernelGGL(k_tiebreak<S>, dim3(grid), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_qr_tall<S>, dim3(grid), dim3(kTallThreads), 0, s, b);
+  }
+  if (!ls.count) return;
   const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.N; });
   bool keep = false;
   for (int r = 0; r < ls.count; ++r) keep = keep || ls.host[r]->tiebreak_keep;

@@ -104,8 +104,8 @@ int validate_impl(const pasd_config* c) {
     if (R > PASD_MAX_RANK)
       return fail(PASD_ERR_UNSUPPORTED, "rank above " + std::to_string(PASD_MAX_RANK));
     if (c->dims[n] > (1 << 30)) return fail(PASD_ERR_UNSUPPORTED, "dimension too large");
-    if (c->dims[n] * R > (R <= kRT ? 8192 : 16384))
-      return fail(PASD_ERR_UNSUPPORTED, R <= kRT ? "I_n * R_n above 8192 (QR workspace)"
+    if (c->dims[n] * R > (R <= kRT ? (1 << 20) : 16384))
+      return fail(PASD_ERR_UNSUPPORTED, R <= kRT ? "I_n * R_n above 2^20"
                                                  : "I_n * R_n above 16384 (QR workspace)");
     if (!isfinite(c->lambda[n]) || !isfinite(c->alpha[n]))
       return fail(PASD_ERR_INVALID_ARG, "lambda and alpha must be finite");

@@ -53,7 +53,8 @@ def test_defaults_follow_algorithm_1():
     (dict(dims=(50, 50, 50), ranks=(17, 5, 5)), 0),                           # two rank tiles
     (dict(dims=(100, 100, 100), ranks=(64, 5, 5)), 0),                        # R = 64
     (dict(dims=(100, 100, 100), ranks=(65, 5, 5)), binding.ERR_UNSUPPORTED),  # R > 64
-    (dict(dims=(1000, 20, 20), ranks=(9, 5, 5)), binding.ERR_UNSUPPORTED),    # I R > 8192
+    (dict(dims=(1000, 20, 20), ranks=(9, 5, 5)), 0),                          # tall mode
+    (dict(dims=(70000, 4, 4), ranks=(16, 4, 4)), binding.ERR_UNSUPPORTED),   # I R > 2^20
     (dict(dims=(1000, 40, 40), ranks=(17, 5, 5)), binding.ERR_UNSUPPORTED),   # I R > 16384
     (dict(dims=(900, 40, 40), ranks=(18, 5, 5)), 0),                          # I R <= 16384
     (dict(dims=(0, 50, 50)), binding.ERR_INVALID_ARG),

@@ -94,6 +94,10 @@ SHAPES = [
     # (A_N mod 16 < R_N): rows past A must be masked in the row operand only
     ((7, 5, 20), (3, 3, 8), 0.01, 30),
     ((111, 41, 36), (7, 14, 8), 0.01, 20),
+    # tall modes (I_n R_n > 8192): the block-wide CholeskyQR2 on M_n in global
+    # memory, and the eigensolver reading U_n from global memory
+    ((1000, 12, 10), (10, 4, 4), 0.01, 25),
+    ((2100, 8, 6), (16, 4, 3), 0.01, 12),
 ]
 
 
@@ -294,3 +298,29 @@ def test_penalty_cap_binds():
     s.step(30)
     assert float(s.export(P.Q_SCALARS)[1]) == 2.0
     _compare(st, s, "fp64", "mu_max binds k=30")
+
+
+def test_tall_mode_rank_deficient_m_fp64():
+    # An exactly rank-3 tensor without corruption and a tall first mode with
+    # R_0 = 12 (I_0 R_0 = 10800): M_0 = G_0 P_0^T is numerically rank
+    # deficient, the tall kernel's CholeskyQR2 pivots fail and its Householder
+    # QR completes the basis.  The completion is not determined (reading R1),
+    # so what holds for any completion is checked: U_n orthonormal, the SVT
+    # ranks reaching the planted rank, and recovery (the oracle's own solve of
+    # this tensor takes 58 iterations to ranks (3, 3, 3) and RSE 1.5e-12).
+    dims, core, ranks = (900, 24, 20), (3, 3, 3), (12, 8, 8)
+    wl = workloads.tucker_workload("talldef", dims, core, 0.0, 17124800, scale="rms", ranks=ranks)
+    s = P.Solver(wl.T, ranks, precision="fp64", tol=1e-9, max_iter=2000, mu0=0.01)
+    for K in (2, 10, 25):
+        s.step(K - s.query().iterations)
+        orth = max(float(np.abs(s.export(P.Q_U, n).T @ s.export(P.Q_U, n) - np.eye(ranks[n])).max())
+                   for n in range(3))
+        print(f"tall rank-deficient M k={K}: orth {orth:.2e} rank {list(s.query().rank[:3])}",
+              flush=True)
+        assert orth <= 1e-12
+    info = s.solve()
+    rse = rel(s.export(P.Q_X), wl.L)
+    print(f"tall rank-deficient M: k={info.iterations} converged={info.converged} "
+          f"rank={list(info.rank[:3])} RSE={rse:.2e}", flush=True)
+    assert info.converged == 1 and list(info.rank[:3]) == [3, 3, 3]
+    assert rse <= 1e-8
