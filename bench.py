@@ -65,22 +65,23 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def kernel_bytes(dims, ranks, es):
+def kernel_bytes(dims, ranks, es, merged=0):
     """Algorithmic HBM bytes per launch of the streaming kernels.
 
     fused : reads T and Y_1..Y_N, writes D and Y_1..Y_N  -> (2N + 2) numel s
             plus one read of every P_n (R_n J_n s)
     gemm_p: reads D and Y_n for every mode               -> 2 N numel s, writes P_n
-    gemm_m: reads D and Y_n for every mode               -> 2 N numel s, reads P_n
+    gemm_m: reads D and Y_n for every mode it computes   -> 2 (N - merged) numel s, reads
+            those P_n (the fused pass accumulates modes 0 .. merged-1 from what it streams)
     """
     import math
     N = len(dims)
     numel = math.prod(dims)
-    Pbytes = sum(r * numel // d for d, r in zip(dims, ranks)) * es
+    pb = [r * numel // d * es for d, r in zip(dims, ranks)]
     return {
-        "fused": (2 * N + 2) * numel * es + Pbytes,
-        "gemm_p": 2 * N * numel * es + Pbytes,
-        "gemm_m": 2 * N * numel * es + Pbytes,
+        "fused": (2 * N + 2) * numel * es + sum(pb),
+        "gemm_p": 2 * N * numel * es + sum(pb),
+        "gemm_m": 2 * (N - merged) * numel * es + sum(pb[merged:]),
     }
 
 
@@ -361,8 +362,9 @@ def _timed_iterations(T, ranks, prec, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     prof = s.profile(max(10, min(steps, 100)))
+    merged = s.query().merged_modes
     s.close()
-    return ms, {k: {"ms": t / max(c, 1)} for k, (t, c) in prof.items()}
+    return ms, {k: {"ms": t / max(c, 1)} for k, (t, c) in prof.items()}, merged
 
 
 def cpu_info():
@@ -428,11 +430,11 @@ def main():
     T32 = wlh.observed(np.float32)
     T64 = T32.astype(np.float64)
     hprec = args.precision
-    ms_per_step, kernels = _timed_iterations(T64 if hprec == "fp64" else T32, ranks, hprec,
-                                             args.steps, args.warmup)
+    ms_per_step, kernels, merged = _timed_iterations(T64 if hprec == "fp64" else T32, ranks,
+                                                     hprec, args.steps, args.warmup)
     value = 1000.0 / ms_per_step
     _progress(f"{args.workload} {hprec}: timed {args.steps} iterations: {ms_per_step:.4f} ms each")
-    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4)
+    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4, merged)
     for k, b in kb.items():
         kernels[k]["alg_bytes"] = b
         kernels[k]["GB/s"] = b / (kernels[k]["ms"] * 1e-3) / 1e9
@@ -466,14 +468,17 @@ def main():
                    "dims": list(dims), "ranks": list(ranks), "tol": wlh.tol},
         "roofline": roofline,
         "kernel_sum_ms": round(ksum, 5),
+        "merged_modes": merged,
+        "iteration_alg_bytes": int(sum(kb.values())),
+        "iteration_alg_GBps": round(sum(kb.values()) / (ms_per_step * 1e-3) / 1e9, 1),
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
     }
 
     # mixed precision on the same workload: FP32 state and GEMMs, FP64 QR/eig/norms
     if not args.no_mixed and args.workload == "c4":
-        ms32, k32 = _timed_iterations(T32, ranks, "fp32", args.steps, args.warmup)
-        ms16, _ = _timed_iterations(T32, ranks, "bf16", args.steps, args.warmup)
+        ms32, k32, _ = _timed_iterations(T32, ranks, "fp32", args.steps, args.warmup)
+        ms16, _, _ = _timed_iterations(T32, ranks, "bf16", args.steps, args.warmup)
         out["mixed"] = {"fp32": {"ms_per_step": round(ms32, 5), "iters_per_s": round(1e3 / ms32, 1),
                                  "kernels_ms": {k: round(v["ms"], 4) for k, v in k32.items()}},
                         "bf16": {"ms_per_step": round(ms16, 5), "iters_per_s": round(1e3 / ms16, 1)}}

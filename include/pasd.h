@@ -127,6 +127,10 @@ typedef struct {
                                        residuals all fall below it but not below tol stops with
                                        done = 4 and converged = 0 (PASD_PRECISION_FLOOR) unless
                                        PASD_FLAG_NO_FLOOR_STOP is set */
+  int merged_modes;                 /* modes 0 .. merged_modes-1 whose G_n P_n^T (eq. (10)) the
+                                       fused pass of the previous iteration accumulates instead
+                                       of a separate unfolding GEMM (0 or 2; order-4 tensors
+                                       whose last two dimensions hold at least 256 vectors) */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;

@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "pasd_internal.hpp"
 
@@ -286,13 +287,86 @@ __device__ __forceinline__ void recon_row(const FusedView<S, NN, IT>& v, int n, 
   }
 }
 
+// Merged modes (Problem::mmerge): the columns P_n[:, j .. j + VEC) of a
+// chunk of a mode n < N-1, the loads recon_row issues for that mode.
+template <typename S, int NN, int VEC, int RP, typename IT>
+__device__ __forceinline__ void merged_cols(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
+                                            IT& in, S (&pv)[RP][VEC]) {
+  const IT q1 = div_fixed<IT>(row, v.Rb[n], v.frb[n]);
+  const IT a = n == 0 ? IT(0) : div_fixed<IT>(q1, v.I[n], v.fi[n]);  // A_0 = 1
+  in = q1 - a * v.I[n];
+  const IT j = a * v.B[n] + (row - q1 * v.Rb[n]) * v.IN + i;
+#pragma unroll
+  for (int r = 0; r < RP; ++r) gload<S, VEC, IT>(v.P[n], (IT)r * v.J[n] + j, pv[r]);
+}
+
+// recon_row of a merged mode, keeping the P_n columns for the GEMM-M sums.
+template <typename S, typename ZT, int NN, int VEC, int RP, typename IT>
+__device__ __forceinline__ void recon_row_keep(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
+                                               ZT z[VEC], S (&pv)[RP][VEC]) {
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
+  IT in;
+  merged_cols<S, NN, VEC, RP, IT>(v, n, row, i, in, pv);
+  constexpr int W = VW<S>::n;
+  constexpr int RU = (RP + W - 1) / W * W;
+  S u[RU];
+#pragma unroll
+  for (int r = 0; r < RU; r += W) gload<S, W, IT>(v.F[n], in * (IT)kRT + (IT)r, &u[r]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < RP; ++r)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
+}
+
+// GEMM-M of the next iteration for one merged mode at one chunk:
+// acc[r] += G(x) P_n[r, j(x)] with G = D + Y_n / mu (state type, one fused
+// multiply-add, as the GEMM-M kernels form it) and FP64 products and sums.
+template <typename S, int VEC, int RP>
+__device__ __forceinline__ void macc_add(double (&acc)[RP], const S (&pv)[RP][VEC],
+                                         const S (&d)[VEC], const S (&y)[VEC], S inv_mu) {
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) {
+    const S g = fma(y[t], inv_mu, d[t]);
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc[r] = fma((double)g, (double)pv[r][t], acc[r]);
+  }
+}
+
+// The block's partial sums of the merged modes' M_n rows (blockDim = 256,
+// fixed-order reduction: wave butterflies, then the four waves in order),
+// written to Mf_n[b][0 .. RP).
+template <typename S, int MM, int RP>
+__device__ __forceinline__ void macc_store(const Problem<S>& pb, const double (&acc)[MM][RP],
+                                           int b) {
+  __shared__ double red[4][MM * RP];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int n = 0; n < MM; ++n)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) {
+      double v = acc[n][r];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) red[wave][n * RP + r] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < MM * RP) {
+    const int n = threadIdx.x / RP, r = threadIdx.x % RP;
+    const double v = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                     red[3][threadIdx.x];
+    pb.m[n].Mf[(int64_t)b * kRT + r] = v;
+  }
+}
+
 // One problem's share of the fused pass: `nblk` blocks of which this is `lblk`.
 // The arithmetic is in the state type: every quantity is formed with one
 // rounding from stored state-type values (D - Z_n of two nearby values is
 // exact, Y_n + mu (D - Z_n) is one fused multiply-add), so wider registers would
 // change the stored iterate only through the rounding of mu.  The residual is
 // taken from the stored D.
-template <typename S, int NN, int VEC, int RP, typename IT, bool SPLIT1>
+template <typename S, int NN, int VEC, int RP, typename IT, bool SPLIT1, int MM>
 __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int nblk, bool xcd_split) {
   // Accumulation type of Z_n and type of the elementwise arithmetic.  Both are
   // the state type: wider registers were measured to leave FP32 convergence
@@ -305,6 +379,9 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   const ET inv_mu = (ET)(1.0 / mu_d);
   const ET theta = (ET)(1.0 / (mu_d * NN));
   const ET invN = (ET)(1.0 / NN);
+  // the penalty of the next iteration, as the control kernel forms it, for
+  // the merged modes' G = D + Y_n / mu
+  const S inv_mu_next = (S)(1.0 / fmin(pb.rho * mu_d, pb.mu_max));
   AbsMax<ET> rmax[NN + 1];  // residual of every mode, then max |D|
   // Blocks are dealt to the 8 XCDs in turn (block b to XCD b mod 8).  When the
   // problem's blocks split evenly, the blocks of one XCD sweep (grid-stride)
@@ -315,7 +392,18 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   // of its mode-1 eighth: chunk = (e / f_seg) f_cp0 + x f_seg + e mod f_seg.
   IT c0 = 0, c1 = v.nchunk, first = (IT)lblk * blockDim.x, step = (IT)nblk * blockDim.x;
   IT seg_base = 0;
-  if (xcd_split) {
+  // merged modes: block lblk sweeps its own mcb consecutive chunks
+  double macc[MM > 0 ? MM : 1][RP > 0 ? RP : 1];
+  if constexpr (MM > 0) {
+#pragma unroll
+    for (int n = 0; n < MM; ++n)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) macc[n][r] = 0.0;
+    c0 = (IT)lblk * (IT)pb.mcb;
+    c1 = c0 + (IT)pb.mcb;
+    first = 0;
+    step = blockDim.x;
+  } else if (xcd_split) {
     const int x = lblk % kXcds;
     first = (IT)(lblk / kXcds) * blockDim.x;
     step = (IT)(nblk / kXcds) * blockDim.x;
@@ -346,8 +434,17 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     // factor loads
 #pragma unroll
     for (int n = 0; n < NN; ++n) gload<S, VEC, IT>(v.Y[n], x0, y[n]);
+    S pk[MM > 0 ? MM : 1][RP > 0 ? RP : 1][VEC];
 #pragma unroll
-    for (int n = 0; n < NN; ++n) recon_row<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n]);
+    for (int n = 0; n < NN; ++n) {
+      if constexpr (MM > 0) {
+        if (n < MM) {
+          recon_row_keep<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n], pk[n < MM ? n : 0]);
+          continue;
+        }
+      }
+      recon_row<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n]);
+    }
     S dv[VEC];
 #pragma unroll
     for (int t = 0; t < VEC; ++t) {
@@ -370,7 +467,12 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     gstore<S, VEC, IT>(v.D, x0, dv);
 #pragma unroll
     for (int n = 0; n < NN; ++n) gstore<S, VEC, IT>(v.Y[n], x0, y[n]);
+    if constexpr (MM > 0) {
+#pragma unroll
+      for (int n = 0; n < MM; ++n) macc_add<S, VEC, RP>(macc[n], pk[n], dv, y[n], inv_mu_next);
+    }
   }
+  if constexpr (MM > 0) macc_store<S, MM, RP>(pb, macc, lblk);
   double r[NN + 1];
 #pragma unroll
   for (int n = 0; n <= NN; ++n) r[n] = rmax[n].get();
@@ -379,7 +481,7 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
 
 // The fused pass over a batch; each problem takes the 16-byte vector path when
 // its last dimension is a multiple of the vector width.
-template <typename S, int NN, int RP, typename IT, bool SPLIT1>
+template <typename S, int NN, int RP, typename IT, bool SPLIT1, int MM>
 __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
   const Problem<S>& pb = *bt.p[req];
@@ -392,15 +494,61 @@ __global__ void __launch_bounds__(256) k_fused(Batch<S> bt) {
     // launched only for one problem with fsplit1 set and a grid of whole
     // XCD rounds (a separate instantiation keeps the other's registers low)
     if (pb.vecw)
-      fused_body<S, NN, VW<S>::n, RP, IT, true>(pb, lblk, nblk, true);
+      fused_body<S, NN, VW<S>::n, RP, IT, true, 0>(pb, lblk, nblk, true);
     else
-      fused_body<S, NN, 1, RP, IT, true>(pb, lblk, nblk, true);
+      fused_body<S, NN, 1, RP, IT, true, 0>(pb, lblk, nblk, true);
   } else {
     if (pb.vecw)
-      fused_body<S, NN, VW<S>::n, RP, IT, false>(pb, lblk, nblk, xcd_split);
+      fused_body<S, NN, VW<S>::n, RP, IT, false, MM>(pb, lblk, nblk, xcd_split);
     else
-      fused_body<S, NN, 1, RP, IT, false>(pb, lblk, nblk, xcd_split);
+      fused_body<S, NN, 1, RP, IT, false, MM>(pb, lblk, nblk, xcd_split);
   }
+}
+
+// The merged modes' GEMM-M partials recomputed from the stored D, Y_n and
+// P_n (after a checkpoint import, which restores the iterate but not these
+// sums): the fused pass's traversal, loads and arithmetic, so the partials
+// equal those the pass itself would have written.
+template <typename S, int NN, int VEC, int RP, int MM>
+__device__ __forceinline__ void mrefresh_body(const Problem<S>& pb, int lblk) {
+  typedef uint32_t IT;
+  const FusedView<S, NN, IT> v = fused_view<S, NN, VEC, IT>(pb);
+  const S inv_mu = (S)(1.0 / pb.sc->mu);
+  double macc[MM][RP];
+#pragma unroll
+  for (int n = 0; n < MM; ++n)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) macc[n][r] = 0.0;
+  const IT c0 = (IT)lblk * (IT)pb.mcb, c1 = c0 + (IT)pb.mcb;
+  for (IT c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const IT row = div_fixed<IT>(c, v.Q, v.fq);
+    const IT i = (c - row * v.Q) * VEC;
+    const IT x0 = c * VEC;
+    S dv[VEC];
+    gload<S, VEC, IT>(v.D, x0, dv);
+    S y[MM][VEC];
+    S pv[MM][RP][VEC];
+#pragma unroll
+    for (int n = 0; n < MM; ++n) {
+      gload<S, VEC, IT>(v.Y[n], x0, y[n]);
+      IT in;
+      merged_cols<S, NN, VEC, RP, IT>(v, n, row, i, in, pv[n]);
+    }
+#pragma unroll
+    for (int n = 0; n < MM; ++n) macc_add<S, VEC, RP>(macc[n], pv[n], dv, y[n], inv_mu);
+  }
+  macc_store<S, MM, RP>(pb, macc, lblk);
+}
+
+template <typename S, int NN, int RP, int MM>
+__global__ void __launch_bounds__(256) k_mrefresh(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  const int lblk = blockIdx.x - bt.start[req];
+  if (pb.vecw)
+    mrefresh_body<S, NN, VW<S>::n, RP, MM>(pb, lblk);
+  else
+    mrefresh_body<S, NN, 1, RP, MM>(pb, lblk);
 }
 
 // One wave: fold the residual slots (and clear them for the next iteration),
@@ -546,85 +694,166 @@ static int elem_grid(int64_t work) {
 
 int fused_blocks(int64_t numel, int vec) { return elem_grid(numel / vec); }
 
-template <typename S, int NN, int RP>
+// The fused pass folds in the GEMM-M of modes 0 and 1 (order 4, ranks within
+// one tile, 32-bit offsets) when the mode-1 slab, S = B_1 / vec chunks with one
+// index i_1, holds at least one block sweep of 256 chunks: blocks of mcb
+// chunks, mcb the smallest divisor of S not below max(256, nchunk / 4096), so
+// that every block lies inside one slab of both merged modes and the grid
+// stays near the 4096 blocks of the plain pass.  (Measured: at 64^4 the two
+// merged modes take GEMM-M from 214 to 126 us and leave the pass at 375 us;
+// folding in one mode of a 3-way tensor, 200^3 FP32 or the video-shaped
+// workload, costs the pass more than it saves, since the kept P_n columns and
+// sums halve its occupancy.)
+void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, bool idx32,
+                int* mmerge, int64_t* mcb, int* blocks) {
+  *mmerge = 0;
+  *mcb = 0;
+  *blocks = fused_blocks(numel, vec);
+  if (!idx32 || max_rank > kRT || N != 4) return;
+  const int64_t nchunk = numel / vec;
+  for (int d = 1; d >= 1; --d) {
+    int64_t B = 1;
+    for (int m = d + 1; m < N; ++m) B *= dims[m];
+    if (B % vec) continue;
+    const int64_t S = B / vec;
+    if (S < 256) continue;
+    int64_t cb = std::max<int64_t>(256, (nchunk + 4095) / 4096);
+    if (cb >= S) cb = S;
+    while (S % cb) ++cb;
+    const int64_t nb = nchunk / cb;
+    if (nb > 65535) return;
+    *mmerge = d + 1;
+    *mcb = cb;
+    *blocks = (int)nb;
+    return;
+  }
+}
+
+template <typename S, int NN, int RP, int MM>
 static void fused_idx(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.fused_blocks; });
-  bool idx32 = true;
-  for (int r = 0; r < ls.count; ++r) idx32 = idx32 && ls.host[r]->idx32;
-  // the mode-1 order over the XCDs (Problem::fsplit1) for a launch of one
-  // problem whose blocks fill whole XCD rounds; the traversal order changes
-  // no result
-  const bool split1 = idx32 && ls.count == 1 && ls.host[0]->fsplit1 && grid % kXcds == 0;
-  if (split1)
-    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, true>), dim3(grid), dim3(256), 0, s, b);
-  else if (idx32)
-    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, false>), dim3(grid), dim3(256), 0, s, b);
-  else  // offsets beyond 32 bits: 64-bit indexing, full rank tile (or the tile loop)
-    hipLaunchKernelGGL((k_fused<S, NN, RP == 0 ? 0 : kRT, uint64_t, false>), dim3(grid), dim3(256), 0,
-                       s, b);
+  if constexpr (MM > 0) {
+    // merged problems (32-bit offsets by construction)
+    hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, false, MM>), dim3(grid), dim3(256), 0, s, b);
+  } else {
+    bool idx32 = true;
+    for (int r = 0; r < ls.count; ++r) idx32 = idx32 && ls.host[r]->idx32;
+    // the mode-1 order over the XCDs (Problem::fsplit1) for a launch of one
+    // problem whose blocks fill whole XCD rounds; the traversal order changes
+    // no result
+    const bool split1 = idx32 && ls.count == 1 && ls.host[0]->fsplit1 && grid % kXcds == 0;
+    if (split1)
+      hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, true, 0>), dim3(grid), dim3(256), 0, s, b);
+    else if (idx32)
+      hipLaunchKernelGGL((k_fused<S, NN, RP, uint32_t, false, 0>), dim3(grid), dim3(256), 0, s, b);
+    else  // offsets beyond 32 bits: 64-bit indexing, full rank tile (or the tile loop)
+      hipLaunchKernelGGL((k_fused<S, NN, RP == 0 ? 0 : kRT, uint64_t, false, 0>), dim3(grid),
+                         dim3(256), 0, s, b);
+  }
+}
+
+template <typename S, int NN, int RP, int MM>
+static void mrefresh_idx(const LaunchSet<S>& ls, hipStream_t s) {
+  Batch<S> b;
+  const int grid = make_batch(ls, b, [](const Problem<S>& p) { return p.fused_blocks; });
+  hipLaunchKernelGGL((k_mrefresh<S, NN, RP, MM>), dim3(grid), dim3(256), 0, s, b);
 }
 
 // The rank loop is unrolled to the largest R_n of the set, rounded up to even
-// for orders up to 4 and to a multiple of 4 above.
-template <typename S, int NN>
+// for orders up to 4 and to a multiple of 4 above.  REFRESH: the merged
+// modes' GEMM-M partials only (k_mrefresh).
+template <typename S, int NN, int MM, bool REFRESH = false>
 static void fused_n(const LaunchSet<S>& ls, hipStream_t s) {
   int rmax = 1;
   for (int r = 0; r < ls.count; ++r)
     for (int n = 0; n < ls.host[r]->N; ++n) rmax = std::max(rmax, ls.host[r]->g[n].R);
+  auto go = [&](auto rp) {
+    constexpr int RP = decltype(rp)::value;
+    if constexpr (REFRESH)
+      mrefresh_idx<S, NN, RP, MM>(ls, s);
+    else
+      fused_idx<S, NN, RP, MM>(ls, s);
+  };
   if constexpr (NN <= 4) {
     // orders up to 4: the rank loop is unrolled to R rounded up to even (the
     // pass is bound by its load instructions, one per rank and mode)
     switch ((rmax + 1) / 2) {
-      case 1: fused_idx<S, NN, 2>(ls, s); return;
-      case 2: fused_idx<S, NN, 4>(ls, s); return;
-      case 3: fused_idx<S, NN, 6>(ls, s); return;
-      case 4: fused_idx<S, NN, 8>(ls, s); return;
-      case 5: fused_idx<S, NN, 10>(ls, s); return;
-      case 6: fused_idx<S, NN, 12>(ls, s); return;
-      case 7: fused_idx<S, NN, 14>(ls, s); return;
-      default: fused_idx<S, NN, 16>(ls, s); return;
+      case 1: go(std::integral_constant<int, 2>{}); return;
+      case 2: go(std::integral_constant<int, 4>{}); return;
+      case 3: go(std::integral_constant<int, 6>{}); return;
+      case 4: go(std::integral_constant<int, 8>{}); return;
+      case 5: go(std::integral_constant<int, 10>{}); return;
+      case 6: go(std::integral_constant<int, 12>{}); return;
+      case 7: go(std::integral_constant<int, 14>{}); return;
+      default: go(std::integral_constant<int, 16>{}); return;
     }
   } else {
     if (rmax <= 4)
-      fused_idx<S, NN, 4>(ls, s);
+      go(std::integral_constant<int, 4>{});
     else if (rmax <= 8)
-      fused_idx<S, NN, 8>(ls, s);
+      go(std::integral_constant<int, 8>{});
     else if (rmax <= 12)
-      fused_idx<S, NN, 12>(ls, s);
+      go(std::integral_constant<int, 12>{});
     else
-      fused_idx<S, NN, 16>(ls, s);
+      go(std::integral_constant<int, 16>{});
+  }
+}
+
+// Problems of a set by their number of merged modes (0, 1 or 2).
+template <typename S>
+static void split_merged(const LaunchSet<S>& ls, LaunchSet<S> (&out)[3]) {
+  for (int m = 0; m < 3; ++m) out[m].count = 0;
+  for (int r = 0; r < ls.count; ++r) {
+    LaunchSet<S>& d = out[ls.host[r]->mmerge];
+    d.host[d.count] = ls.host[r];
+    d.dev[d.count] = ls.dev[r];
+    ++d.count;
   }
 }
 
 // All problems of a set have the same order N (the batch driver groups them).
-// Problems with some R_n > kRT take the tile-looped rank path (RP = 0).
+// Problems with some R_n > kRT take the tile-looped rank path (RP = 0);
+// problems with merged modes (order 4 only) their own instantiations.
 template <typename S>
 void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
   LaunchSet<S> nar, wid;
   split_wide(ls, nar, wid);
   if (nar.count) {
-    switch (nar.host[0]->N) {
-      case 2: fused_n<S, 2>(nar, s); break;
-      case 3: fused_n<S, 3>(nar, s); break;
-      case 4: fused_n<S, 4>(nar, s); break;
-      case 5: fused_n<S, 5>(nar, s); break;
-      case 6: fused_n<S, 6>(nar, s); break;
-      case 7: fused_n<S, 7>(nar, s); break;
-      default: fused_n<S, 8>(nar, s); break;
+    LaunchSet<S> mg[3];
+    split_merged(nar, mg);
+    const int N = nar.host[0]->N;
+    if (mg[0].count) {
+      switch (N) {
+        case 2: fused_n<S, 2, 0>(mg[0], s); break;
+        case 3: fused_n<S, 3, 0>(mg[0], s); break;
+        case 4: fused_n<S, 4, 0>(mg[0], s); break;
+        case 5: fused_n<S, 5, 0>(mg[0], s); break;
+        case 6: fused_n<S, 6, 0>(mg[0], s); break;
+        case 7: fused_n<S, 7, 0>(mg[0], s); break;
+        default: fused_n<S, 8, 0>(mg[0], s); break;
+      }
     }
+    if (mg[2].count) fused_n<S, 4, 2>(mg[2], s);
   }
   if (wid.count) {
     switch (wid.host[0]->N) {
-      case 2: fused_idx<S, 2, 0>(wid, s); break;
-      case 3: fused_idx<S, 3, 0>(wid, s); break;
-      case 4: fused_idx<S, 4, 0>(wid, s); break;
-      case 5: fused_idx<S, 5, 0>(wid, s); break;
-      case 6: fused_idx<S, 6, 0>(wid, s); break;
-      case 7: fused_idx<S, 7, 0>(wid, s); break;
-      default: fused_idx<S, 8, 0>(wid, s); break;
+      case 2: fused_idx<S, 2, 0, 0>(wid, s); break;
+      case 3: fused_idx<S, 3, 0, 0>(wid, s); break;
+      case 4: fused_idx<S, 4, 0, 0>(wid, s); break;
+      case 5: fused_idx<S, 5, 0, 0>(wid, s); break;
+      case 6: fused_idx<S, 6, 0, 0>(wid, s); break;
+      case 7: fused_idx<S, 7, 0, 0>(wid, s); break;
+      default: fused_idx<S, 8, 0, 0>(wid, s); break;
     }
   }
+}
+
+template <typename S>
+void launch_mrefresh(const LaunchSet<S>& ls, hipStream_t s) {
+  LaunchSet<S> mg[3];
+  split_merged(ls, mg);
+  if (mg[2].count) fused_n<S, 4, 2, true>(mg[2], s);
 }
 
 template <typename S>
@@ -655,7 +884,8 @@ void launch_component(const Problem<S>& p, int n, S* Z, hipStream_t s) {
   template void launch_control<S>(const LaunchSet<S>&, hipStream_t);         \
   template void launch_init<S>(const Problem<S>&, double, hipStream_t);      \
   template void launch_output<S>(const Problem<S>&, S*, S*, hipStream_t);    \
-  template void launch_component<S>(const Problem<S>&, int, S*, hipStream_t);
+  template void launch_component<S>(const Problem<S>&, int, S*, hipStream_t); \
+  template void launch_mrefresh<S>(const LaunchSet<S>&, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

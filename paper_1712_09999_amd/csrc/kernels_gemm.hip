@@ -635,7 +635,29 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   const int64_t ne = (int64_t)g.I * g.R;
   __shared__ double part[4][64];
   double acc[4] = {0, 0, 0, 0};
-  if (e < ne) {
+  if (n < pb.mmerge) {
+    // a mode whose GEMM-M the fused pass folds in: M[i][r] is the sum over
+    // the fused blocks of every slab with index i, blocks (a I + i) K + k for
+    // term t = a K + k (a < A, k < K = mslab[n]); group grp sums the terms
+    // grp, grp + 4, ... into acc[(t / 4) % 4], as below
+    if (e < ne) {
+      const int64_t i = e / g.R, r = e - i * g.R;
+      const int64_t K = pb.mslab[n], nt = g.A * K;
+      constexpr int kRM = 16;
+      for (int64_t t0 = grp; t0 < nt; t0 += 4 * kRM) {
+        double v[kRM];
+#pragma unroll
+        for (int u = 0; u < kRM; ++u) {
+          const int64_t t = t0 + 4 * u < nt ? t0 + 4 * u : nt - 1;
+          const int64_t a = t / K, k = t - a * K;
+          v[u] = mb.Mf[((a * g.I + i) * K + k) * kRT + r];
+        }
+#pragma unroll
+        for (int u = 0; u < kRM; ++u)
+          if (t0 + 4 * u < nt) acc[u % 4] += v[u];
+      }
+    }
+  } else if (e < ne) {
     // group grp sums partials grp, grp + 4, ... into acc[(b / 4) % 4]; kRM
     // unconditional loads per pass (index clamped, value masked) are in
     // flight together

@@ -78,6 +78,7 @@ struct ModeBufs {
   double* Wf;    // RT x RT SVT factor
   double* Wev;   // RT x RT eigenvectors of the last Gram (warm start)
   double* Fac;   // RT SVT weights f_i of the last eigensolve (f_i > 0: V_n keeps direction i)
+  double* Mf;    // merged modes: the fused pass's partials of the next M_n, [fused_blocks][kRT]
   int mblocks;   // number of GEMM-M partial blocks
   int sblocks;   // number of Gram partial blocks
 };
@@ -119,6 +120,17 @@ struct Problem {
   int fsplit1;
   uint32_t f_cp0, f_cp1, f_seg;
   FastDiv fd_seg;
+  // GEMM-M of the next iteration folded into the fused pass for the modes
+  // 0 .. mmerge-1 (mmerge > 0): the pass runs fused_blocks blocks, block b over
+  // the mcb consecutive chunks from b mcb on, a range inside one mode-n slab
+  // (B_n consecutive elements, one index i_n) for every merged mode; each
+  // block writes its partial sums of M_n[i_n, :] = sum G_n(x) P_n[:, j_n(x)]
+  // over its range to ModeBufs::Mf, and the GEMM-M reduction adds the
+  // mslab[n] blocks of every slab with index i_n.  GEMM-M has no blocks for
+  // these modes.
+  int mmerge;
+  uint32_t mcb;
+  int mslab[kMaxN];
   // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
   // the rows per mode-n fibre index (B_n / I_N) and I_n
   FastDiv fd_q;
@@ -223,6 +235,15 @@ template <typename S> void launch_control(const LaunchSet<S>& ls, hipStream_t s)
 template <typename S> void launch_init(const Problem<S>& p, double mu0, hipStream_t s);
 template <typename S> void launch_output(const Problem<S>& p, S* X, S* E, hipStream_t s);
 template <typename S> void launch_component(const Problem<S>& p, int n, S* Z, hipStream_t s);
+// Recompute the merged modes' GEMM-M partials from the stored state (after a
+// checkpoint import), with the fused pass's own arithmetic and order.
+template <typename S> void launch_mrefresh(const LaunchSet<S>& ls, hipStream_t s);
+
+// Modes whose GEMM-M folds into the fused pass (see Problem::mmerge): for a
+// tensor of order N with last-mode vector width vec and nchunk = numel / vec
+// chunks, sets *mmerge (0: none), *mcb (chunks per fused block) and *blocks.
+void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, bool idx32,
+                int* mmerge, int64_t* mcb, int* blocks);
 
 // Grid sizes chosen on the host.
 int gemm_m_blocks(const ModeGeom& g, int N);

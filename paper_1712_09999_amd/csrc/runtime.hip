@@ -81,6 +81,9 @@ struct pasd_ctx {
   hipGraphExec_t graph = nullptr;
   bool graph_disabled = false;
   void* dev_prob = nullptr;  // device copy of pd / pf, inside `base`
+  // an import changed the iterate: the merged modes' GEMM-M partials are
+  // recomputed before the next iteration (see Problem::mmerge)
+  bool mrefresh = false;
 };
 
 namespace {
@@ -133,6 +136,11 @@ struct Plan {
   ModeGeom geom[kMaxN];
   int mblocks[kMaxN], sblocks[kMaxN];
   int64_t numel;
+  // fused pass: vector width of the last mode, 32-bit offsets, blocks, and
+  // the modes whose GEMM-M it folds in (merge_plan)
+  int vec, idx32, fblocks, mmerge;
+  int64_t mcb;
+  size_t off_Mf[kMaxN];
 };
 
 void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
@@ -141,6 +149,8 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
   int64_t numel = 1;
   for (int n = 0; n < N; ++n) numel *= c->dims[n];
   p.numel = numel;
+  int rmax = 1;
+  int64_t span = numel;
   for (int n = 0; n < N; ++n) {
     ModeGeom& g = p.geom[n];
     g.A = 1;
@@ -151,8 +161,16 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
     g.J = g.A * g.B;
     g.R = (int)c->ranks[n];
     g.T = (g.R + kRT - 1) / kRT;
-    p.mblocks[n] = gemm_m_blocks(g, N);
-    p.sblocks[n] = gram_blocks(g);
+    rmax = std::max(rmax, g.R);
+    span = std::max<int64_t>(span, (int64_t)kRT * g.T * g.J);
+  }
+  const int vw = 16 / (int)es;
+  p.vec = (c->dims[N - 1] % vw) == 0 ? vw : 1;
+  p.idx32 = span * (int64_t)es < (int64_t(1) << 31) ? 1 : 0;
+  merge_plan(c->dims, N, numel, p.vec, rmax, p.idx32 != 0, &p.mmerge, &p.mcb, &p.fblocks);
+  for (int n = 0; n < N; ++n) {
+    p.mblocks[n] = n < p.mmerge ? 0 : gemm_m_blocks(p.geom[n], N - p.mmerge);
+    p.sblocks[n] = gram_blocks(p.geom[n]);
   }
   p.off_T = own_T ? p.L.add(numel * es) : 0;  // T read in place when not owned
   p.off_D = p.L.add(numel * es);
@@ -175,6 +193,7 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
     p.off_Wf[n] = p.L.add(RT * RT * 8);
     p.off_Wev[n] = p.L.add(RT * RT * 8);
     p.off_Fac[n] = p.L.add(RT * 8);
+    p.off_Mf[n] = n < p.mmerge ? p.L.add((size_t)p.fblocks * kRT * 8) : 0;
   }
 }
 
@@ -203,6 +222,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     m.Wf = reinterpret_cast<double*>(b + pl.off_Wf[n]);
     m.Wev = reinterpret_cast<double*>(b + pl.off_Wev[n]);
     m.Fac = reinterpret_cast<double*>(b + pl.off_Fac[n]);
+    m.Mf = n < pl.mmerge ? reinterpret_cast<double*>(b + pl.off_Mf[n]) : nullptr;
     m.mblocks = pl.mblocks[n];
     m.sblocks = pl.sblocks[n];
     p.lam[n] = ctx->lam[n];
@@ -226,20 +246,23 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     p.kb[KB_GRAM][n + 1] = p.kb[KB_GRAM][n] + p.m[n].sblocks;
   }
   const int vw = 16 / (int)sizeof(S);
-  p.vecw = (p.g[ctx->N - 1].I % vw) == 0 ? 1 : 0;
-  p.fused_blocks = fused_blocks(p.numel, p.vecw ? vw : 1);
+  p.vecw = pl.vec == vw ? 1 : 0;
+  p.fused_blocks = pl.fblocks;
   // 32-bit offsets in the fused pass when every element offset, and every
   // index divided there, stays below 2^31 bytes
-  int64_t span = p.numel;
-  for (int n = 0; n < ctx->N; ++n) span = std::max<int64_t>(span, (int64_t)kRT * p.g[n].T * p.g[n].J);
-  p.idx32 = span * (int64_t)sizeof(S) < (int64_t(1) << 31) ? 1 : 0;
+  p.idx32 = pl.idx32;
+  p.mmerge = pl.mmerge;
+  p.mcb = (uint32_t)pl.mcb;
+  for (int n = 0; n < kMaxN; ++n)
+    p.mslab[n] = n < pl.mmerge ? (int)(p.g[n].B / pl.vec / pl.mcb) : 0;
   const int64_t IN = p.g[ctx->N - 1].I;
   p.fd_q = make_fastdiv((uint32_t)(p.idx32 ? IN / (p.vecw ? vw : 1) : 1));
   // Mode-1 order of the fused pass when P_0 would not stay in one XCD's L2
   // (4 MB, shared with the streamed tensors): more than 2 MiB of P_0.
   const int64_t vec = p.vecw ? vw : 1;
   const int64_t p0_bytes = (int64_t)p.g[0].R * p.g[0].J * (int64_t)sizeof(S);
-  p.fsplit1 = (ctx->N >= 3 && p.idx32 && p.g[1].I % kXcds == 0 && p0_bytes > (int64_t(2) << 20)) ? 1 : 0;
+  p.fsplit1 = (p.mmerge == 0 && ctx->N >= 3 && p.idx32 && p.g[1].I % kXcds == 0 &&
+               p0_bytes > (int64_t(2) << 20)) ? 1 : 0;
   p.f_cp1 = p.fsplit1 ? (uint32_t)(p.g[1].B / vec) : 1;
   p.f_cp0 = p.fsplit1 ? (uint32_t)(p.g[0].B / vec) : 1;
   p.f_seg = p.fsplit1 ? p.f_cp1 * (uint32_t)(p.g[1].I / kXcds) : 1;
@@ -382,7 +405,30 @@ void ensure_graph(pasd_ctx* ctx) {
   ctx->graph_disabled = false;
 }
 
+// After an import, the merged modes' GEMM-M partials of the restored iterate
+// (launched directly, never captured).
+void refresh_merged(pasd_ctx* ctx, hipStream_t s) {
+  if (!ctx->mrefresh) return;
+  ctx->mrefresh = false;
+  if (ctx->cfg.precision == PASD_FP64) {
+    if (!ctx->pd.mmerge) return;
+    LaunchSet<double> ls;
+    ls.count = 1;
+    ls.host[0] = &ctx->pd;
+    ls.dev[0] = static_cast<const Problem<double>*>(ctx->dev_prob);
+    launch_mrefresh<double>(ls, s);
+  } else {
+    if (!ctx->pf.mmerge) return;
+    LaunchSet<float> ls;
+    ls.count = 1;
+    ls.host[0] = &ctx->pf;
+    ls.dev[0] = static_cast<const Problem<float>*>(ctx->dev_prob);
+    launch_mrefresh<float>(ls, s);
+  }
+}
+
 int enqueue(pasd_ctx* ctx, int count, hipEvent_t* ev = nullptr) {
+  if (count > 0) refresh_merged(ctx, ctx->stream);
   // The graph is captured and instantiated on the first enqueue of any
   // length, so that a caller's warm-up (even one iteration) absorbs that cost
   // and later calls replay it.
@@ -419,6 +465,7 @@ void fill_info(pasd_ctx* ctx, pasd_info* info) {
     info->tol_effective = s->tol_eff;
   }
   info->bytes_resident = ctx->bytes;
+  info->merged_modes = ctx->cfg.precision == PASD_FP64 ? ctx->pd.mmerge : ctx->pf.mmerge;
 }
 
 struct DeviceGuard {
@@ -783,6 +830,7 @@ int pasd_import(pasd_ctx* ctx, int q, int index, const void* src, int on_device)
   const size_t es = ctx->elem;
   const hipMemcpyKind kind = (hipMemcpyKind)copy_kind(on_device);
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->mrefresh = true;
   switch (q) {
     case PASD_Q_E: {
       // D = T - E, computed on the host side of the copy to keep one code path
@@ -938,6 +986,7 @@ void enqueue_batch(pasd_ctx* const* ctxs, int count, int n_iters, hipStream_t s)
 // A captured batched step: n_iters iterations of a fixed set of contexts,
 // replayed as one graph on the contexts' stream.
 struct pasd_batch {
+  std::vector<pasd_ctx*> ctxs;
   int dev = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -952,6 +1001,7 @@ int pasd_step_batch(pasd_ctx* const* ctxs, int count, int n_iters) {
   if (rc != PASD_OK) return rc;
   if (count == 0 || n_iters == 0) return PASD_OK;
   DeviceGuard guard(ctxs[0]->dev);
+  for (int i = 0; i < count; ++i) refresh_merged(ctxs[i], ctxs[i]->stream);
   enqueue_batch(ctxs, count, n_iters, ctxs[0]->stream);
   HIP_TRY(hipGetLastError());
   return PASD_OK;
@@ -975,7 +1025,9 @@ int pasd_batch_create(pasd_ctx* const* ctxs, int count, int n_iters, pasd_batch*
   if (rc != PASD_OK) return rc;
   if (count == 0 || n_iters < 1) return fail(PASD_ERR_INVALID_ARG, "empty batch");
   DeviceGuard guard(ctxs[0]->dev);
+  for (int i = 0; i < count; ++i) refresh_merged(ctxs[i], ctxs[i]->stream);
   pasd_batch* b = new pasd_batch();
+  b->ctxs.assign(ctxs, ctxs + count);
   b->dev = ctxs[0]->dev;
   b->stream = ctxs[0]->stream;
   hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
@@ -1005,6 +1057,7 @@ int pasd_batch_step(pasd_batch* b) {
   g_last_error.clear();
   if (!b || !b->exec) return fail(PASD_ERR_INVALID_ARG, "batch is NULL");
   DeviceGuard guard(b->dev);
+  for (pasd_ctx* c : b->ctxs) refresh_merged(c, b->stream);
   HIP_TRY(hipGraphLaunch(b->exec, b->stream));
   return PASD_OK;
 }

@@ -72,6 +72,7 @@ class Info(ctypes.Structure):
         ("bytes_resident", ctypes.c_size_t),
         ("eig_sweeps", ctypes.c_int * MAX_ORDER),
         ("tol_effective", ctypes.c_double),
+        ("merged_modes", ctypes.c_int),
     ]
 
 

@@ -203,6 +203,48 @@ def test_checkpoint_restore_is_bitwise():
     np.testing.assert_array_equal(b.export(P.Q_E), a.export(P.Q_E))
 
 
+# 4-way with a mode-1 slab of 512 (FP64) or 256 (FP32) chunks: the fused pass folds in the
+# GEMM-M of modes 0 and 1 (blocks of 256 chunks)
+MERGED = ((12, 10, 32, 32), (3, 4, 3, 3))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_merged_gemm_m_trajectory(precision):
+    dims, ranks = MERGED
+    wl = workloads.tucker_workload("merged", dims, (3, 3, 3, 3), 0.1, 17125100,
+                                   value_range=(-5, 5), scale="rms")
+    T = wl.observed(np.float32 if precision == "fp32" else np.float64).astype(np.float64)
+    st = pasd_init(T, ranks, mu0=0.01)
+    s = _gpu(T, ranks, precision, mu0=0.01)
+    done = 0
+    for K in (1, 2, 15, 40):
+        pasd_iterate(st, K - done)
+        s.step(K - done)
+        done = K
+        _compare(st, s, precision, f"merged {precision} k={K}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_merged_checkpoint_restore_is_bitwise(precision):
+    # the restore does not carry the fused pass's GEMM-M partials of the merged
+    # modes; they are recomputed from the restored iterate before it continues
+    dims, ranks = MERGED
+    wl = workloads.tucker_workload("merged", dims, (3, 3, 3, 3), 0.1, 17125100,
+                                   value_range=(-5, 5), scale="rms")
+    T = wl.observed(np.float32 if precision == "fp32" else np.float64)
+    a = _gpu(T, ranks, precision, mu0=0.01)
+    a.step(30)
+    ck = a.checkpoint()
+    a.step(20)
+    b = _gpu(T, ranks, precision, mu0=0.01)
+    b.step(3)  # a different state before the restore
+    b.restore(ck)
+    b.step(20)
+    np.testing.assert_array_equal(b.export(P.Q_D), a.export(P.Q_D))
+    for n in range(4):
+        np.testing.assert_array_equal(b.export(P.Q_Y, n), a.export(P.Q_Y, n))
+
+
 def test_runs_are_bitwise_reproducible():
     wl = workloads.make_config("c1")
     outs = []
