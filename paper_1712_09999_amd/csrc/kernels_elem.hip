@@ -320,6 +320,39 @@ __device__ __forceinline__ void recon_row_keep(const FusedView<S, NN, IT>& v, in
     for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
 }
 
+// recon_row_keep with the mode's U_n W_f row already in registers (a merged
+// mode's index i_n is the same for every chunk of a block).
+template <typename S, typename ZT, int NN, int VEC, int RP, int RU, typename IT>
+__device__ __forceinline__ void recon_keep_u(const FusedView<S, NN, IT>& v, int n, IT row, IT i,
+                                             ZT z[VEC], S (&pv)[RP][VEC], const S (&u)[RU]) {
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
+  IT in;
+  merged_cols<S, NN, VEC, RP, IT>(v, n, row, i, in, pv);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < RP; ++r)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
+}
+
+// recon_row of the last mode with its (U W)^T columns i .. i + VEC already in
+// registers.
+template <typename S, typename ZT, int NN, int VEC, int RP, typename IT>
+__device__ __forceinline__ void recon_last_u(const FusedView<S, NN, IT>& v, IT row, ZT z[VEC],
+                                             const S (&u)[RP][VEC]) {
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
+  S pr[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r) gload<S, 1, IT>(v.P[NN - 1], (IT)r * v.J[NN - 1] + row, &pr[r]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int r = 0; r < RP; ++r)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r][t], (ZT)pr[r], z[t]);
+}
+
 // GEMM-M of the next iteration for one merged mode at one chunk:
 // acc[r] += G(x) P_n[r, j(x)] with G = D + Y_n / mu (state type, one fused
 // multiply-add, as the GEMM-M kernels form it) and FP64 products and sums.
@@ -394,6 +427,21 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   IT seg_base = 0;
   // merged modes: block lblk sweeps its own mcb consecutive chunks
   double macc[MM > 0 ? MM : 1][RP > 0 ? RP : 1];
+  // The U_n W_f rows of the merged modes are the same for the whole block
+  // (its chunks lie in one slab of each), and when the row length in chunks
+  // divides the block's start and stride, so are the last mode's columns for
+  // all chunks of a thread: both are loaded once, before the sweep (64^4
+  // FP64: 374 -> 350 us).  With an FP32 state, keeping the last mode's
+  // columns was measured slower (173 -> 189 us; the compiler then holds every
+  // load of a chunk before the first product), the merged rows alone faster
+  // (169 us).
+  constexpr bool kHoistU = MM > 0;
+  constexpr bool kHoistLast = MM > 0 && sizeof(S) == 8;
+  constexpr int RPk = RP > 0 ? RP : 1;
+  constexpr int RUk = (RPk + VW<S>::n - 1) / VW<S>::n * VW<S>::n;
+  S um[MM > 0 ? MM : 1][RUk];
+  S ul[RPk][VEC];
+  bool keep_last = false;
   if constexpr (MM > 0) {
 #pragma unroll
     for (int n = 0; n < MM; ++n)
@@ -403,6 +451,22 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     c1 = c0 + (IT)pb.mcb;
     first = 0;
     step = blockDim.x;
+    const IT row0 = div_fixed<IT>(c0, v.Q, v.fq);
+#pragma unroll
+    for (int n = 0; n < (kHoistU ? MM : 0); ++n) {
+      const IT q1 = div_fixed<IT>(row0, v.Rb[n], v.frb[n]);
+      const IT a = n == 0 ? IT(0) : div_fixed<IT>(q1, v.I[n], v.fi[n]);
+      const IT in = q1 - a * v.I[n];
+#pragma unroll
+      for (int r = 0; r < RUk; r += VW<S>::n)
+        gload<S, VW<S>::n, IT>(v.F[n], in * (IT)kRT + (IT)r, &um[n][r]);
+    }
+    keep_last = kHoistLast && ((IT)blockDim.x % v.Q) == 0 && ((IT)pb.mcb % v.Q) == 0;
+    if (keep_last) {
+      const IT i0 = ((IT)threadIdx.x % v.Q) * VEC;
+#pragma unroll
+      for (int r = 0; r < RPk; ++r) gload<S, VEC, IT>(v.F[NN - 1], (IT)r * v.IN + i0, ul[r]);
+    }
   } else if (xcd_split) {
     const int x = lblk % kXcds;
     first = (IT)(lblk / kXcds) * blockDim.x;
@@ -439,7 +503,15 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     for (int n = 0; n < NN; ++n) {
       if constexpr (MM > 0) {
         if (n < MM) {
-          recon_row_keep<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n], pk[n < MM ? n : 0]);
+          if constexpr (kHoistU)
+            recon_keep_u<S, ZT, NN, VEC, RP, RUk, IT>(v, n, row, i, z[n], pk[n < MM ? n : 0],
+                                                      um[n < MM ? n : 0]);
+          else
+            recon_row_keep<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n], pk[n < MM ? n : 0]);
+          continue;
+        }
+        if (n == NN - 1 && keep_last) {
+          recon_last_u<S, ZT, NN, VEC, RPk, IT>(v, row, z[n], ul);
           continue;
         }
       }

@@ -992,13 +992,171 @@ void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s) {
   for_tile_sets(ls, [s](const LaunchSet<S>& t) { launch_reduce_m_set(t, s); });
 }
 
+// ---------------------------------------------------------------------------
+// Gram S = P P^T on the vector ALUs for ranks up to 8: each thread takes
+// 16-byte chunks of columns of P_n (4 floats or 2 doubles), UR chunks per
+// pass with every load in flight, and accumulates the upper triangle of the
+// outer products in FP64 registers.  The block reduces them in a fixed order:
+// within each 16-lane row by DPP exchanges (lanes i^1, i^2, then the mirror
+// images within 8 and within 16 lanes; a + b and b + a round alike, so every
+// lane of a row ends with the same row sum), then the 16 row sums of the
+// block in LDS, in row order.  At these ranks the 16-wide FP64 MFMA tile of
+// k_gram spends most of its work on padding and waits for its loads once per
+// round of products (64^4, R_n = 6: FP64 24.6 -> 17.1 us, FP32 22.8 -> 13.3
+// us); at R_n = 10 the MFMA kernel is the faster one (9.7 against 11.4 us at
+// 200^3 FP32).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_mirror
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int NT>
+__device__ __forceinline__ void row_sums(double (&acc)[NT]) {
+  double t[NT];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppXor1>(acc[e]);
+#pragma unroll
+  for (int e = 0; e < NT; ++e) acc[e] += t[e];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppXor2>(acc[e]);
+#pragma unroll
+  for (int e = 0; e < NT; ++e) acc[e] += t[e];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppHalfMirror>(acc[e]);
+#pragma unroll
+  for (int e = 0; e < NT; ++e) acc[e] += t[e];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppMirror>(acc[e]);
+#pragma unroll
+  for (int e = 0; e < NT; ++e) acc[e] += t[e];
+}
+
+template <typename S, int RP>
+__global__ void __launch_bounds__(256) k_gram_v(Batch<S> bt) {
+  typedef S v16 __attribute__((ext_vector_type(16 / sizeof(S))));
+  constexpr int W = 16 / sizeof(S);
+  constexpr int NT = RP * (RP + 1) / 2;
+  constexpr int UR = (RP * W * sizeof(S) / 4 <= 24) ? 4 : 2;  // chunks per pass
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done) return;
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_GRAM], pb.N, lb);
+  const int blk = lb - pb.kb[KB_GRAM][n];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int R = g.R;
+  const int64_t nch = (g.J + W - 1) / W;
+  const int64_t per = (nch + mb.sblocks - 1) / mb.sblocks;
+  const int64_t q0 = (int64_t)blk * per, q1 = min(nch, q0 + per);
+  const bool vec = (g.J % W) == 0;
+  double acc[NT];
+#pragma unroll
+  for (int e = 0; e < NT; ++e) acc[e] = 0.0;
+  const PASD_GLOBAL S* rows[RP];
+#pragma unroll
+  for (int r = 0; r < RP; ++r)
+    rows[r] = (const PASD_GLOBAL S*)(mb.P + (int64_t)(r < R ? r : R - 1) * g.J);
+  for (int64_t qb = q0 + threadIdx.x; qb < q1; qb += 256 * UR) {
+    S x[UR][RP][W];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const int64_t q = qb + 256 * u;
+      const int64_t qc = q < q1 ? q : q0;  // clamped, masked below
+      if (vec) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+          const v16 v = *(const PASD_GLOBAL v16*)(rows[r] + qc * W);
+#pragma unroll
+          for (int t = 0; t < W; ++t) x[u][r][t] = v[t];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < RP; ++r)
+#pragma unroll
+          for (int t = 0; t < W; ++t) {
+            const int64_t j = qc * W + t;
+            x[u][r][t] = rows[r][j < g.J ? j : g.J - 1];
+          }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const int64_t q = qb + 256 * u;
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const bool ok = q < q1 && q * W + t < g.J;
+        double xv[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) xv[r] = (ok && r < R) ? (double)x[u][r][t] : 0.0;
+        int e = 0;
+#pragma unroll
+        for (int r = 0; r < RP; ++r)
+#pragma unroll
+          for (int c = r; c < RP; ++c, ++e) acc[e] = fma(xv[r], xv[c], acc[e]);
+      }
+    }
+  }
+  row_sums<NT>(acc);
+  __shared__ double red[16][NT];
+  if ((threadIdx.x & 15) == 0) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) red[threadIdx.x >> 4][e] = acc[e];
+  }
+  __syncthreads();
+  {
+    // entry (r, c) of the 16 x 16 partial, both triangles
+    const int r = threadIdx.x / kRT, c = threadIdx.x % kRT;
+    const int lo = r < c ? r : c, hi = r < c ? c : r;
+    double v = 0.0;
+    if (hi < RP) {
+      const int e = lo * RP - lo * (lo - 1) / 2 + (hi - lo);
+#pragma unroll
+      for (int w = 0; w < 16; ++w) v += red[w][e];
+    }
+    mb.Spart[(int64_t)blk * kRT * kRT + threadIdx.x] = v;
+  }
+}
+
 template <typename S>
 void launch_gram(const LaunchSet<S>& ls, hipStream_t s) {
   LaunchSet<S> nar, wid;
   split_wide(ls, nar, wid);
   Batch<S> b;
-  if (nar.count) {
-    const int tot = make_batch(nar, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
+  // problems whose ranks are all at most 8 take the vector-ALU Gram (the
+  // choice is per problem, so a solve's partials are the same alone and in a
+  // batch); the others the FP64 MFMA one
+  LaunchSet<S> v, m;
+  v.count = m.count = 0;
+  int rv = 1;
+  for (int r = 0; r < nar.count; ++r) {
+    int rm = 1;
+    for (int n = 0; n < nar.host[r]->N; ++n) rm = std::max(rm, nar.host[r]->g[n].R);
+    LaunchSet<S>& d = rm <= 8 ? v : m;
+    if (rm <= 8) rv = std::max(rv, rm);
+    d.host[d.count] = nar.host[r];
+    d.dev[d.count] = nar.dev[r];
+    ++d.count;
+  }
+  if (v.count) {
+    const int tot = make_batch(v, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
+    switch ((rv + 1) / 2) {
+      case 1: hipLaunchKernelGGL((k_gram_v<S, 2>), dim3(tot), dim3(256), 0, s, b); break;
+      case 2: hipLaunchKernelGGL((k_gram_v<S, 4>), dim3(tot), dim3(256), 0, s, b); break;
+      case 3: hipLaunchKernelGGL((k_gram_v<S, 6>), dim3(tot), dim3(256), 0, s, b); break;
+      default: hipLaunchKernelGGL((k_gram_v<S, 8>), dim3(tot), dim3(256), 0, s, b); break;
+    }
+  }
+  if (m.count) {
+    const int tot = make_batch(m, b, [](const Problem<S>& p) { return mode_grid(p, KB_GRAM); });
     hipLaunchKernelGGL(k_gram<S>, dim3(tot), dim3(256), 0, s, b);
   }
   if (wid.count) {

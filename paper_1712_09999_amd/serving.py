@@ -4,11 +4,12 @@ Requests (one TRPCA solve each) arrive over time.  The loop admits arrived
 requests while a slot is free and their device footprint (pasd_footprint)
 fits the HBM budget, keeps every admitted solve resident on the GPU, and
 advances all of them together: each step is `step_iters` iterations of every
-resident solve as grouped kernel launches, replayed from a HIP graph captured
-for the current resident set (pasd_batch_create / pasd_batch_step; captured
-again whenever a solve is admitted or retired) or, with graphs=False,
-launched directly (pasd_step_batch), followed by one batched status read
-(pasd_query_batch).  Solves that converged or hit their
+resident solve as grouped kernel launches, followed by one batched status
+read (pasd_query_batch).  The grouped step is launched directly
+(pasd_step_batch) while the resident set changes; once the same set has been
+stepped `graph_after` times in a row it is captured as a HIP graph
+(pasd_batch_create) and replayed (pasd_batch_step) until a solve is admitted
+or retired (graphs=False: always direct).  Solves that converged or hit their
 iteration cap are retired (results copied out, device memory released) and
 their slots go to waiting requests.  A request's latency is its completion
 time minus its arrival time, queueing included.
@@ -61,10 +62,11 @@ class Result:
 class Server:
     def __init__(self, precision: str = "fp32", max_slots: int = 64,
                  hbm_budget: Optional[int] = None, step_iters: int = 4, device: int = 0,
-                 keep_results: bool = True, graphs: bool = True):
+                 keep_results: bool = True, graphs: bool = True, graph_after: int = 2):
         import torch
         self.precision = precision
         self.graphs = bool(graphs)
+        self.graph_after = int(graph_after)
         self.max_slots = int(max_slots)
         self.step_iters = int(step_iters)
         self.device = device
@@ -93,6 +95,7 @@ class Server:
         captures = 0
         graph = None  # BatchGraph of the current resident set
         graph_set: tuple = ()
+        stable = 0  # consecutive steps of the current set
         t0 = time.perf_counter()
         while pending or active:
             now = time.perf_counter() - t0
@@ -115,14 +118,18 @@ class Server:
                         time.sleep(min(wait, 0.01))
                 continue
             solvers = [a[1] for a in active]
-            if self.graphs:
-                key = tuple(id(x) for x in solvers)
-                if graph is None or key != graph_set:
-                    if graph is not None:
-                        graph.close()
-                    graph = P.BatchGraph(solvers, self.step_iters)
-                    graph_set = key
-                    captures += 1
+            key = tuple(id(x) for x in solvers)
+            if key != graph_set:
+                if graph is not None:
+                    graph.close()
+                    graph = None
+                graph_set = key
+                stable = 0
+            stable += 1
+            if graph is None and self.graphs and stable > self.graph_after:
+                graph = P.BatchGraph(solvers, self.step_iters)
+                captures += 1
+            if graph is not None:
                 graph.step()
             else:
                 P.step_batch(solvers, self.step_iters)
@@ -140,6 +147,7 @@ class Server:
                     if graph is not None:  # the graph holds this solve's state
                         graph.close()
                         graph = None
+                    graph_set = ()
                     s.close()
                     used -= fp
                 else:
