@@ -393,6 +393,30 @@ __device__ __forceinline__ void macc_store(const Problem<S>& pb, const double (&
   }
 }
 
+// Z_n from a factor row staged in LDS: u (U_n W_f row, or the last mode's P
+// column) read as 16-byte vectors, times the VEC columns pv already loaded.
+template <typename S, typename ZT, int VEC, int RP, int RU>
+__device__ __forceinline__ void recon_lds(const S* u_lds, const S (&pv)[RP][VEC], ZT z[VEC]) {
+  constexpr int W = VW<S>::n;
+  S u[RU];
+#pragma unroll
+  for (int r = 0; r < RU; r += W) {
+    const typename VW<S>::t x = *reinterpret_cast<const typename VW<S>::t*>(u_lds + r);
+#pragma unroll
+    for (int t = 0; t < W; ++t) u[r + t] = x[t];
+  }
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) z[t] = ZT(0);
+#pragma unroll
+  for (int r = 0; r < RP; ++r)
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) z[t] = fma((ZT)u[r], (ZT)pv[r][t], z[t]);
+}
+
+// Rows staged per block for the order-4 merged pass (mode 2's U W rows and the
+// last mode's P columns of the block's rows).
+constexpr int kStageRows = 128;
+
 // One problem's share of the fused pass: `nblk` blocks of which this is `lblk`.
 // The arithmetic is in the state type: every quantity is formed with one
 // rounding from stored state-type values (D - Z_n of two nearby values is
@@ -442,6 +466,16 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   S um[MM > 0 ? MM : 1][RUk];
   S ul[RPk][VEC];
   bool keep_last = false;
+  // Order-4 merged blocks with an FP64 state stage mode 2's U W rows and the
+  // last mode's P columns for their rows (at most kStageRows) in LDS, once per
+  // block, in place of 9 global loads per chunk (64^4 R_n = 6: 350 -> 326 us;
+  // with an FP32 state it gained nothing).  P_n and U_n W_f have zero rows /
+  // columns up to kRT, so the padded reads stay in bounds.
+  constexpr bool kStage = MM > 0 && NN == 4 && RP > 0 && sizeof(S) == 8;
+  __shared__ __align__(16) S st_f[kStage ? kStageRows : 1][RUk];
+  __shared__ __align__(16) S st_p[kStage ? kStageRows : 1][RUk];
+  bool staged = false;
+  IT st_row0 = 0;
   if constexpr (MM > 0) {
 #pragma unroll
     for (int n = 0; n < MM; ++n)
@@ -466,6 +500,29 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
       const IT i0 = ((IT)threadIdx.x % v.Q) * VEC;
 #pragma unroll
       for (int r = 0; r < RPk; ++r) gload<S, VEC, IT>(v.F[NN - 1], (IT)r * v.IN + i0, ul[r]);
+    }
+    if constexpr (kStage) {
+      // the block's rows row0 .. row0 + nrows - 1: mode NN-2's U W rows at
+      // their indices i_{NN-2} and the last mode's P columns at the rows
+      st_row0 = row0;
+      const IT nrows = div_fixed<IT>(c1 - 1, v.Q, v.fq) - row0 + 1;
+      staged = nrows <= (IT)kStageRows;
+      if (staged) {
+        constexpr int n2 = NN - 2;
+        for (IT e = threadIdx.x; e < nrows * (IT)RUk; e += blockDim.x) {
+          const IT k = e / (IT)RUk, r = e - k * (IT)RUk;
+          const IT row = row0 + k;
+          const IT q1 = div_fixed<IT>(row, v.Rb[n2], v.frb[n2]);
+          const IT a = div_fixed<IT>(q1, v.I[n2], v.fi[n2]);
+          const IT in = q1 - a * v.I[n2];
+          S f, pc;
+          gload<S, 1, IT>(v.F[n2], in * (IT)kRT + r, &f);
+          gload<S, 1, IT>(v.P[NN - 1], r * v.J[NN - 1] + row, &pc);
+          st_f[k][r] = f;
+          st_p[k][r] = pc;
+        }
+      }
+      __syncthreads();
     }
   } else if (xcd_split) {
     const int x = lblk % kXcds;
@@ -509,6 +566,33 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
           else
             recon_row_keep<S, ZT, NN, VEC, RP, IT>(v, n, row, i, z[n], pk[n < MM ? n : 0]);
           continue;
+        }
+        if constexpr (kStage) {
+          if (staged && n == NN - 2) {
+            S pv[RPk][VEC];
+            IT in;
+            merged_cols<S, NN, VEC, RPk, IT>(v, n, row, i, in, pv);
+            __builtin_amdgcn_sched_barrier(0);
+            recon_lds<S, ZT, VEC, RPk, RUk>(&st_f[row - st_row0][0], pv, z[n]);
+            continue;
+          }
+          if (staged && n == NN - 1 && keep_last) {
+            S pr[RUk];
+#pragma unroll
+            for (int r = 0; r < RUk; r += VW<S>::n) {
+              const typename VW<S>::t x =
+                  *reinterpret_cast<const typename VW<S>::t*>(&st_p[row - st_row0][r]);
+#pragma unroll
+              for (int t = 0; t < VW<S>::n; ++t) pr[r + t] = x[t];
+            }
+#pragma unroll
+            for (int t = 0; t < VEC; ++t) z[n][t] = ZT(0);
+#pragma unroll
+            for (int r = 0; r < RPk; ++r)
+#pragma unroll
+              for (int t = 0; t < VEC; ++t) z[n][t] = fma((ZT)ul[r][t], (ZT)pr[r], z[n][t]);
+            continue;
+          }
         }
         if (n == NN - 1 && keep_last) {
           recon_last_u<S, ZT, NN, VEC, RPk, IT>(v, row, z[n], ul);
@@ -768,28 +852,34 @@ int fused_blocks(int64_t numel, int vec) { return elem_grid(numel / vec); }
 
 // The fused pass folds in the GEMM-M of modes 0 and 1 (order 4, ranks within
 // one tile, 32-bit offsets) when the mode-1 slab, S = B_1 / vec chunks with one
-// index i_1, holds at least one block sweep of 256 chunks: blocks of mcb
-// chunks, mcb the smallest divisor of S not below max(256, nchunk / 4096), so
+// index i_1, holds at least four block sweeps of 256 chunks: blocks of mcb
+// chunks, mcb the smallest divisor of S not below max(1024, nchunk / 4096), so
 // that every block lies inside one slab of both merged modes and the grid
-// stays near the 4096 blocks of the plain pass.  (Measured: at 64^4 the two
-// merged modes take GEMM-M from 214 to 126 us and leave the pass at 375 us;
-// folding in one mode of a 3-way tensor, 200^3 FP32 or the video-shaped
-// workload, costs the pass more than it saves, since the kept P_n columns and
-// sums halve its occupancy.)
-void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, bool idx32,
-                int* mmerge, int64_t* mcb, int* blocks) {
+// stays near the 4096 blocks of the plain pass.  Measured (per iteration,
+// merged against separate GEMM-M): 64^4 FP64 R_n = 6 0.707 against 0.837 ms,
+// R_n = 16 1.218 against 1.242; FP32 R_n = 6, 8, 10 0.368 / 0.402 / 0.445
+// against 0.413 / 0.436 / 0.474 ms, but R_n = 12 0.611 against 0.503 (the
+// kept P_n columns and sums take the FP32 pass to one wave per SIMD), so FP32
+// states merge up to rank 10.  Blocks of fewer sweeps spend too much on their
+// set-up and the partial sums: 32 x 48 x 40 x 56 (S = 560 FP32 chunks, one
+// sweep) ran the pass at 79 against 40 us.  Folding in one mode of a 3-way
+// tensor, 200^3 FP32 or the video-shaped workload, costs the pass more than it
+// saves, since the kept P_n columns and sums halve its occupancy.
+void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, int state_bytes,
+                bool idx32, int* mmerge, int64_t* mcb, int* blocks) {
   *mmerge = 0;
   *mcb = 0;
   *blocks = fused_blocks(numel, vec);
   if (!idx32 || max_rank > kRT || N != 4) return;
+  if (state_bytes == 4 && max_rank > 10) return;
   const int64_t nchunk = numel / vec;
   for (int d = 1; d >= 1; --d) {
     int64_t B = 1;
     for (int m = d + 1; m < N; ++m) B *= dims[m];
     if (B % vec) continue;
     const int64_t S = B / vec;
-    if (S < 256) continue;
-    int64_t cb = std::max<int64_t>(256, (nchunk + 4095) / 4096);
+    if (S < 1024) continue;
+    int64_t cb = std::max<int64_t>(1024, (nchunk + 4095) / 4096);
     if (cb >= S) cb = S;
     while (S % cb) ++cb;
     const int64_t nb = nchunk / cb;

@@ -242,8 +242,8 @@ template <typename S> void launch_mrefresh(const LaunchSet<S>& ls, hipStream_t s
 // Modes whose GEMM-M folds into the fused pass (see Problem::mmerge): for a
 // tensor of order N with last-mode vector width vec and nchunk = numel / vec
 // chunks, sets *mmerge (0: none), *mcb (chunks per fused block) and *blocks.
-void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, bool idx32,
-                int* mmerge, int64_t* mcb, int* blocks);
+void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, int state_bytes,
+                bool idx32, int* mmerge, int64_t* mcb, int* blocks);
 
 // Grid sizes chosen on the host.
 int gemm_m_blocks(const ModeGeom& g, int N);

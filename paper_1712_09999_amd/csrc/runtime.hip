@@ -167,7 +167,7 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
   const int vw = 16 / (int)es;
   p.vec = (c->dims[N - 1] % vw) == 0 ? vw : 1;
   p.idx32 = span * (int64_t)es < (int64_t(1) << 31) ? 1 : 0;
-  merge_plan(c->dims, N, numel, p.vec, rmax, p.idx32 != 0, &p.mmerge, &p.mcb, &p.fblocks);
+  merge_plan(c->dims, N, numel, p.vec, rmax, (int)es, p.idx32 != 0, &p.mmerge, &p.mcb, &p.fblocks);
   for (int n = 0; n < N; ++n) {
     p.mblocks[n] = n < p.mmerge ? 0 : gemm_m_blocks(p.geom[n], N - p.mmerge);
     p.sblocks[n] = gram_blocks(p.geom[n]);

@@ -203,25 +203,52 @@ def test_checkpoint_restore_is_bitwise():
     np.testing.assert_array_equal(b.export(P.Q_E), a.export(P.Q_E))
 
 
-# 4-way with a mode-1 slab of 512 (FP64) or 256 (FP32) chunks: the fused pass folds in the
-# GEMM-M of modes 0 and 1 (blocks of 256 chunks)
-MERGED = ((12, 10, 32, 32), (3, 4, 3, 3))
+# 4-way with a mode-1 slab of 4096 (FP64) or 2048 (FP32) chunks: the fused pass folds in the
+# GEMM-M of modes 0 and 1 (blocks of 1024 chunks, several per slab), with the last mode's
+# columns kept per thread and, in FP64, mode 2's U W rows and the last mode's P columns
+# staged in LDS
+MERGED = ((3, 4, 64, 128), (3, 4, 3, 3))
+MERGED_SHAPES = [
+    MERGED,
+    # FP64 only: rows of 48 chunks (the last mode's columns reloaded per chunk)
+    ((2, 3, 40, 96), (2, 3, 3, 4)),
+    # FP64 only: 300 rows per block, more than the LDS stage holds
+    ((2, 2, 300, 8), (2, 2, 4, 3)),
+    # FP32 rank 10: the largest rank merged with an FP32 state
+    ((2, 3, 64, 64), (2, 3, 10, 10)),
+]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_merged_gemm_m_trajectory(precision):
-    dims, ranks = MERGED
-    wl = workloads.tucker_workload("merged", dims, (3, 3, 3, 3), 0.1, 17125100,
+@pytest.mark.parametrize("dims,ranks", MERGED_SHAPES)
+def test_merged_gemm_m_trajectory(dims, ranks, precision):
+    wl = workloads.tucker_workload("merged", dims, tuple(min(r, 3) for r in ranks), 0.1, 17125100,
                                    value_range=(-5, 5), scale="rms")
     T = wl.observed(np.float32 if precision == "fp32" else np.float64).astype(np.float64)
     st = pasd_init(T, ranks, mu0=0.01)
     s = _gpu(T, ranks, precision, mu0=0.01)
+    # the merge plan: FP32 slabs of 40 x 96 and 300 x 8 hold fewer than 1024 chunks
+    fp32_small = precision == "fp32" and dims[2] * dims[3] < 4096
+    assert s.query().merged_modes == (0 if fp32_small else 2), (dims, precision)
     done = 0
     for K in (1, 2, 15, 40):
         pasd_iterate(st, K - done)
         s.step(K - done)
         done = K
-        _compare(st, s, precision, f"merged {precision} k={K}")
+        _compare(st, s, precision, f"merged {dims}/{ranks}/{precision} k={K}")
+
+
+def test_merge_plan_limits():
+    """Order-4 problems fold GEMM-M of modes 0 and 1 into the fused pass only
+    where that was measured faster: slabs of at least 1024 chunks, and ranks up
+    to 10 with an FP32 state (16 with FP64)."""
+    T = np.zeros((2, 3, 64, 64))
+    for prec, R, want in (("fp64", 16, 2), ("fp32", 10, 2), ("fp32", 12, 0)):
+        with P.Solver(T, (2, 3, R, R), precision=prec, tol=0.0, max_iter=10) as s:
+            assert s.query().merged_modes == want, (prec, R)
+    with P.Solver(np.zeros((32, 48, 40, 56)), (4, 4, 4, 4), precision="fp32", tol=0.0,
+                  max_iter=10) as s:
+        assert s.query().merged_modes == 0
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
