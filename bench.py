@@ -65,23 +65,30 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def kernel_bytes(dims, ranks, es, merged=0):
+def kernel_bytes(dims, ranks, es, merged=0, fused_blocks=0):
     """Algorithmic HBM bytes per launch of the streaming kernels.
 
     fused : reads T and Y_1..Y_N, writes D and Y_1..Y_N  -> (2N + 2) numel s
             plus one read of every P_n (R_n J_n s)
     gemm_p: reads D and Y_n for every mode               -> 2 N numel s, writes P_n
     gemm_m: reads D and Y_n for every mode it computes   -> 2 (N - merged) numel s, reads
-            those P_n (the fused pass accumulates modes 0 .. merged-1 from what it streams)
+            those P_n (the fused pass accumulates modes 0 .. merged-1 from what it streams);
+            with every mode merged that launch is k_msum, which reads the pass's
+            I_n x R_n partials of modes 2 .. N-1 (one per fused block) and writes 64 group
+            sums of each, 8 (fused_blocks + 64) sum I_n R_n bytes
     """
     import math
     N = len(dims)
     numel = math.prod(dims)
     pb = [r * numel // d * es for d, r in zip(dims, ranks)]
+    if merged == N:
+        msum = 8 * (fused_blocks + 64) * sum(d * r for d, r in list(zip(dims, ranks))[2:])
+    else:
+        msum = 2 * (N - merged) * numel * es + sum(pb[merged:])
     return {
         "fused": (2 * N + 2) * numel * es + sum(pb),
         "gemm_p": 2 * N * numel * es + sum(pb),
-        "gemm_m": 2 * (N - merged) * numel * es + sum(pb[merged:]),
+        "gemm_m": msum,
     }
 
 
@@ -362,9 +369,10 @@ def _timed_iterations(T, ranks, prec, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     prof = s.profile(max(10, min(steps, 100)))
-    merged = s.query().merged_modes
+    info = s.query()
     s.close()
-    return ms, {k: {"ms": t / max(c, 1)} for k, (t, c) in prof.items()}, merged
+    return (ms, {k: {"ms": t / max(c, 1)} for k, (t, c) in prof.items()},
+            (info.merged_modes, info.fused_blocks))
 
 
 def cpu_info():
@@ -434,7 +442,8 @@ def main():
                                                      hprec, args.steps, args.warmup)
     value = 1000.0 / ms_per_step
     _progress(f"{args.workload} {hprec}: timed {args.steps} iterations: {ms_per_step:.4f} ms each")
-    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4, merged)
+    merged, fused_blocks = merged
+    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4, merged, fused_blocks)
     for k, b in kb.items():
         kernels[k]["alg_bytes"] = b
         kernels[k]["GB/s"] = b / (kernels[k]["ms"] * 1e-3) / 1e9

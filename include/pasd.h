@@ -129,8 +129,11 @@ typedef struct {
                                        PASD_FLAG_NO_FLOOR_STOP is set */
   int merged_modes;                 /* modes 0 .. merged_modes-1 whose G_n P_n^T (eq. (10)) the
                                        fused pass of the previous iteration accumulates instead
-                                       of a separate unfolding GEMM (0 or 2; order-4 tensors
-                                       whose last two dimensions hold at least 256 vectors) */
+                                       of a separate unfolding GEMM: 0, 2 (order-4 tensors whose
+                                       last two dimensions hold at least 1024 vectors; FP32
+                                       states up to rank 10) or 4 (also the last two modes: FP64
+                                       state, ranks up to 6, rows of at most 64 vectors) */
+  int fused_blocks;                 /* workgroups of one launch of the fused pass */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;

@@ -417,6 +417,117 @@ __device__ __forceinline__ void recon_lds(const S* u_lds, const S (&pv)[RP][VEC]
 // last mode's P columns of the block's rows).
 constexpr int kStageRows = 128;
 
+// Sum of w over the Q aligned lanes of a row group (Q a power of two, at
+// most 64), left in every lane of the group: DPP exchanges within quads (lanes
+// i^1, i^2), the mirror images within 8 and 16 lanes, then lanes i^16 and
+// i^32.  Every lane adds the same two values at each step (a + b and b + a
+// round alike), so the order is fixed.
+template <int NT>
+__device__ __forceinline__ void group_sum(double (&w)[NT], uint32_t Q) {
+  double t[NT];
+  if (Q > 1) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppXor1>(w[e]);
+#pragma unroll
+    for (int e = 0; e < NT; ++e) w[e] += t[e];
+  }
+  if (Q > 2) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppXor2>(w[e]);
+#pragma unroll
+    for (int e = 0; e < NT; ++e) w[e] += t[e];
+  }
+  if (Q > 4) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppHalfMirror>(w[e]);
+#pragma unroll
+    for (int e = 0; e < NT; ++e) w[e] += t[e];
+  }
+  if (Q > 8) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) t[e] = dpp_f64<kDppMirror>(w[e]);
+#pragma unroll
+    for (int e = 0; e < NT; ++e) w[e] += t[e];
+  }
+  if (Q > 16) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) t[e] = __shfl_xor(w[e], 16, 64);
+#pragma unroll
+    for (int e = 0; e < NT; ++e) w[e] += t[e];
+  }
+  if (Q > 32) {
+#pragma unroll
+    for (int e = 0; e < NT; ++e) t[e] = __shfl_xor(w[e], 32, 64);
+#pragma unroll
+    for (int e = 0; e < NT; ++e) w[e] += t[e];
+  }
+}
+
+// The fast modes' GEMM-M terms of one chunk (Problem::mfull), with
+// G_n = D + Y_n / mu formed as in the GEMM-M kernels and FP64 products: the
+// last mode's go to the thread's own sums for its columns (acc3, P_3 column
+// p3 of this row), mode 2's to w, this chunk's share of its row's sum over the
+// thread's columns (P_2 columns p2, the same for every chunk of the thread).
+template <typename S, int VEC, int RP>
+__device__ __forceinline__ void fast_acc(double (&acc3)[VEC][RP], double (&w)[RP],
+                                         const S (&p2)[RP][VEC], const S (&p3)[RP],
+                                         const S (&d)[VEC], const S (&y2)[VEC],
+                                         const S (&y3)[VEC], S inv_mu) {
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) {
+    const S g3 = fma(y3[t], inv_mu, d[t]);
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc3[t][r] = fma((double)g3, (double)p3[r], acc3[t][r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RP; ++r) w[r] = 0.0;
+#pragma unroll
+  for (int t = 0; t < VEC; ++t) {
+    const S g2 = fma(y2[t], inv_mu, d[t]);
+#pragma unroll
+    for (int r = 0; r < RP; ++r) w[r] = fma((double)g2, (double)p2[r][t], w[r]);
+  }
+}
+
+// Block end of the fast modes (Problem::mfull; blockDim = 256): the block's
+// I_2 x R partial of M_2 (its rows' sums m2[k][r] for i_2 = i2a + k, k <
+// nrows, zero elsewhere) and I_3 x R partial of M_3 (for column i_3 = VEC cq
+// + t, the sum over the threads cq, cq + Q, ... of their acc3[t], in thread
+// order) to Mq[lblk].
+template <typename S, int NN, int VEC, int RP>
+__device__ __forceinline__ void fast_store(const Problem<S>& pb, int lblk,
+                                           const double (&acc3)[VEC][RP], const double* m2,
+                                           uint32_t i2a, uint32_t nrows, uint32_t Q) {
+  __shared__ double st_a3[256][VEC * RP];
+#pragma unroll
+  for (int t = 0; t < VEC; ++t)
+#pragma unroll
+    for (int r = 0; r < RP; ++r) st_a3[threadIdx.x][t * RP + r] = acc3[t][r];
+  __syncthreads();
+  {
+    const int R2 = pb.g[NN - 2].R;
+    const uint32_t ne = (uint32_t)pb.g[NN - 2].I * R2;
+    double* q2 = pb.m[NN - 2].Mq + (int64_t)lblk * ne;
+    for (uint32_t e = threadIdx.x; e < ne; e += blockDim.x) {
+      const uint32_t i2 = e / R2, r = e - i2 * R2;
+      q2[e] = (i2 >= i2a && i2 - i2a < nrows) ? m2[(i2 - i2a) * RP + r] : 0.0;
+    }
+  }
+  {
+    const int R3 = pb.g[NN - 1].R;
+    const uint32_t ne = (uint32_t)pb.g[NN - 1].I * R3;
+    double* q3 = pb.m[NN - 1].Mq + (int64_t)lblk * ne;
+    const uint32_t nm = blockDim.x / Q;
+    for (uint32_t e = threadIdx.x; e < ne; e += blockDim.x) {
+      const uint32_t i3 = e / R3, r = e - i3 * R3;
+      const uint32_t cq = i3 / VEC, t = i3 - cq * VEC;
+      double sum = 0.0;
+      for (uint32_t m = 0; m < nm; ++m) sum += st_a3[cq + Q * m][t * RP + r];
+      q3[e] = sum;
+    }
+  }
+}
+
 // One problem's share of the fused pass: `nblk` blocks of which this is `lblk`.
 // The arithmetic is in the state type: every quantity is formed with one
 // rounding from stored state-type values (D - Z_n of two nearby values is
@@ -476,6 +587,18 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   __shared__ __align__(16) S st_p[kStage ? kStageRows : 1][RUk];
   bool staged = false;
   IT st_row0 = 0;
+  // with the last mode's columns fixed per thread, mode 2's P columns are too
+  // (j_2 runs over (i_0, i_1, i_3), and i_0, i_1 are the block's); at rank 8
+  // keeping them pushed the pass past 256 registers (one wave per SIMD, 64^4:
+  // 364 -> 447 us) and they are loaded per chunk
+  constexpr bool kHoistP2 = kStage && RP != 8;
+  S p2k[kHoistP2 ? RPk : 1][VEC];
+  // the fast modes' GEMM-M in the pass (Problem::mfull, ranks up to 6)
+  constexpr bool kFull = kHoistP2 && RP <= 6;
+  bool mfull = false;
+  double acc3[kFull ? VEC : 1][kFull ? RPk : 1];
+  __shared__ double st_m2[kFull ? kStageRows : 1][kFull ? RPk : 1];
+  uint32_t st_i2a = 0, st_nrows = 0;
   if constexpr (MM > 0) {
 #pragma unroll
     for (int n = 0; n < MM; ++n)
@@ -485,6 +608,12 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
     c1 = c0 + (IT)pb.mcb;
     first = 0;
     step = blockDim.x;
+    if constexpr (kFull) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t)
+#pragma unroll
+        for (int r = 0; r < RPk; ++r) acc3[t][r] = 0.0;
+    }
     const IT row0 = div_fixed<IT>(c0, v.Q, v.fq);
 #pragma unroll
     for (int n = 0; n < (kHoistU ? MM : 0); ++n) {
@@ -521,7 +650,18 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
           st_f[k][r] = f;
           st_p[k][r] = pc;
         }
+        if constexpr (kHoistP2) {
+          if (keep_last) {
+            IT in;
+            merged_cols<S, NN, VEC, RPk, IT>(v, NN - 2, row0, ((IT)threadIdx.x % v.Q) * VEC, in,
+                                             p2k);
+            st_i2a = (uint32_t)in;
+            st_nrows = (uint32_t)nrows;
+          }
+        }
       }
+      // the host sets mfull only where both hold
+      mfull = kFull && pb.mfull && staged && keep_last;
       __syncthreads();
     }
   } else if (xcd_split) {
@@ -569,11 +709,20 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
         }
         if constexpr (kStage) {
           if (staged && n == NN - 2) {
-            S pv[RPk][VEC];
-            IT in;
-            merged_cols<S, NN, VEC, RPk, IT>(v, n, row, i, in, pv);
-            __builtin_amdgcn_sched_barrier(0);
-            recon_lds<S, ZT, VEC, RPk, RUk>(&st_f[row - st_row0][0], pv, z[n]);
+            bool done_n = false;
+            if constexpr (kHoistP2) {
+              if (keep_last) {
+                recon_lds<S, ZT, VEC, RPk, RUk>(&st_f[row - st_row0][0], p2k, z[n]);
+                done_n = true;
+              }
+            }
+            if (!done_n) {
+              S pv[RPk][VEC];
+              IT in;
+              merged_cols<S, NN, VEC, RPk, IT>(v, n, row, i, in, pv);
+              __builtin_amdgcn_sched_barrier(0);
+              recon_lds<S, ZT, VEC, RPk, RUk>(&st_f[row - st_row0][0], pv, z[n]);
+            }
             continue;
           }
           if (staged && n == NN - 1 && keep_last) {
@@ -627,8 +776,27 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
 #pragma unroll
       for (int n = 0; n < MM; ++n) macc_add<S, VEC, RP>(macc[n], pk[n], dv, y[n], inv_mu_next);
     }
+    if constexpr (kFull) {
+      if (mfull) {
+        const IT kr = row - st_row0;
+        S p3[RPk];
+#pragma unroll
+        for (int r = 0; r < RPk; ++r) p3[r] = st_p[kr][r];
+        double w[RPk];
+        fast_acc<S, VEC, RPk>(acc3, w, p2k, p3, dv, y[NN - 2], y[NN - 1], inv_mu_next);
+        group_sum<RPk>(w, (uint32_t)v.Q);
+        if ((IT)threadIdx.x % v.Q == 0) {
+#pragma unroll
+          for (int r = 0; r < RPk; ++r) st_m2[kr][r] = w[r];
+        }
+      }
+    }
   }
   if constexpr (MM > 0) macc_store<S, MM, RP>(pb, macc, lblk);
+  if constexpr (kFull) {
+    if (mfull)
+      fast_store<S, NN, VEC, RPk>(pb, lblk, acc3, &st_m2[0][0], st_i2a, st_nrows, (uint32_t)v.Q);
+  }
   double r[NN + 1];
 #pragma unroll
   for (int n = 0; n <= NN; ++n) r[n] = rmax[n].get();
@@ -676,6 +844,25 @@ __device__ __forceinline__ void mrefresh_body(const Problem<S>& pb, int lblk) {
 #pragma unroll
     for (int r = 0; r < RP; ++r) macc[n][r] = 0.0;
   const IT c0 = (IT)lblk * (IT)pb.mcb, c1 = c0 + (IT)pb.mcb;
+  // the fast modes (Problem::mfull): the pass's P_2 columns, sums and order
+  constexpr bool kFull = sizeof(S) == 8 && NN == 4 && RP <= 6;
+  const bool mfull = kFull && pb.mfull;
+  double acc3[kFull ? VEC : 1][kFull ? RP : 1];
+  S p2k[kFull ? RP : 1][VEC];
+  __shared__ double st_m2[kFull ? kStageRows : 1][kFull ? RP : 1];
+  const IT row0 = div_fixed<IT>(c0, v.Q, v.fq);
+  uint32_t i2a = 0;
+  if constexpr (kFull) {
+    if (mfull) {
+#pragma unroll
+      for (int t = 0; t < VEC; ++t)
+#pragma unroll
+        for (int r = 0; r < RP; ++r) acc3[t][r] = 0.0;
+      IT in;
+      merged_cols<S, NN, VEC, RP, IT>(v, NN - 2, row0, ((IT)threadIdx.x % v.Q) * VEC, in, p2k);
+      i2a = (uint32_t)in;
+    }
+  }
   for (IT c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
     const IT row = div_fixed<IT>(c, v.Q, v.fq);
     const IT i = (c - row * v.Q) * VEC;
@@ -692,8 +879,29 @@ __device__ __forceinline__ void mrefresh_body(const Problem<S>& pb, int lblk) {
     }
 #pragma unroll
     for (int n = 0; n < MM; ++n) macc_add<S, VEC, RP>(macc[n], pv[n], dv, y[n], inv_mu);
+    if constexpr (kFull) {
+      if (mfull) {
+        S y2[VEC], y3[VEC], p3[RP];
+        gload<S, VEC, IT>(v.Y[NN - 2], x0, y2);
+        gload<S, VEC, IT>(v.Y[NN - 1], x0, y3);
+#pragma unroll
+        for (int r = 0; r < RP; ++r) gload<S, 1, IT>(v.P[NN - 1], (IT)r * v.J[NN - 1] + row, &p3[r]);
+        double w[RP];
+        fast_acc<S, VEC, RP>(acc3, w, p2k, p3, dv, y2, y3, inv_mu);
+        group_sum<RP>(w, (uint32_t)v.Q);
+        if ((IT)threadIdx.x % v.Q == 0) {
+#pragma unroll
+          for (int r = 0; r < RP; ++r) st_m2[row - row0][r] = w[r];
+        }
+      }
+    }
   }
   macc_store<S, MM, RP>(pb, macc, lblk);
+  if constexpr (kFull) {
+    if (mfull)
+      fast_store<S, NN, VEC, RP>(pb, lblk, acc3, &st_m2[0][0], i2a, (uint32_t)(pb.mcb / v.Q),
+                                 (uint32_t)v.Q);
+  }
 }
 
 template <typename S, int NN, int RP, int MM>
@@ -866,9 +1074,10 @@ int fused_blocks(int64_t numel, int vec) { return elem_grid(numel / vec); }
 // tensor, 200^3 FP32 or the video-shaped workload, costs the pass more than it
 // saves, since the kept P_n columns and sums halve its occupancy.
 void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, int state_bytes,
-                bool idx32, int* mmerge, int64_t* mcb, int* blocks) {
+                bool idx32, int* mmerge, int64_t* mcb, int* blocks, int* mfull) {
   *mmerge = 0;
   *mcb = 0;
+  *mfull = 0;
   *blocks = fused_blocks(numel, vec);
   if (!idx32 || max_rank > kRT || N != 4) return;
   if (state_bytes == 4 && max_rank > 10) return;
@@ -887,6 +1096,12 @@ void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank
     *mmerge = d + 1;
     *mcb = cb;
     *blocks = (int)nb;
+    // the fast modes too (FP64, ranks up to 6) when every chunk of a thread
+    // has the same last-mode columns (Q | 256 and Q | mcb), a row group lies
+    // in one wave (Q <= 64) and the block's rows fit the LDS stage
+    const int64_t Q = dims[N - 1] / vec;
+    *mfull = state_bytes == 8 && max_rank <= 6 && Q <= 64 && 256 % Q == 0 && cb % Q == 0 &&
+             cb / Q <= kStageRows;
     return;
   }
 }
@@ -962,12 +1177,15 @@ static void fused_n(const LaunchSet<S>& ls, hipStream_t s) {
   }
 }
 
-// Problems of a set by their number of merged modes (0, 1 or 2).
+// Problems of a set by their number of merged modes (0, 1 or 2; 3: every
+// mode, Problem::mfull).  The fast modes' code is compiled for ranks up to 6
+// only, so those problems go out in launches of their own, whose rank bound
+// is theirs.
 template <typename S>
-static void split_merged(const LaunchSet<S>& ls, LaunchSet<S> (&out)[3]) {
-  for (int m = 0; m < 3; ++m) out[m].count = 0;
+static void split_merged(const LaunchSet<S>& ls, LaunchSet<S> (&out)[4]) {
+  for (int m = 0; m < 4; ++m) out[m].count = 0;
   for (int r = 0; r < ls.count; ++r) {
-    LaunchSet<S>& d = out[ls.host[r]->mmerge];
+    LaunchSet<S>& d = out[ls.host[r]->mfull ? 3 : ls.host[r]->mmerge];
     d.host[d.count] = ls.host[r];
     d.dev[d.count] = ls.dev[r];
     ++d.count;
@@ -982,7 +1200,7 @@ void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
   LaunchSet<S> nar, wid;
   split_wide(ls, nar, wid);
   if (nar.count) {
-    LaunchSet<S> mg[3];
+    LaunchSet<S> mg[4];
     split_merged(nar, mg);
     const int N = nar.host[0]->N;
     if (mg[0].count) {
@@ -997,6 +1215,7 @@ void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
       }
     }
     if (mg[2].count) fused_n<S, 4, 2>(mg[2], s);
+    if (mg[3].count) fused_n<S, 4, 2>(mg[3], s);
   }
   if (wid.count) {
     switch (wid.host[0]->N) {
@@ -1013,9 +1232,10 @@ void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
 
 template <typename S>
 void launch_mrefresh(const LaunchSet<S>& ls, hipStream_t s) {
-  LaunchSet<S> mg[3];
+  LaunchSet<S> mg[4];
   split_merged(ls, mg);
   if (mg[2].count) fused_n<S, 4, 2, true>(mg[2], s);
+  if (mg[3].count) fused_n<S, 4, 2, true>(mg[3], s);
 }
 
 template <typename S>

@@ -684,6 +684,48 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   }
 }
 
+// First stage of the fast modes' GEMM-M reduction when the fused pass
+// accumulates them (Problem::mfull): the pass leaves one I_n x R partial per
+// block in Mq; block (tile, q) of mode n takes the 64 entries e = 64 tile +
+// lane, and its thread group grp the fused blocks of group g = 4 q + grp (the
+// g-th of kMsumGroups runs of consecutive blocks), summed in block order with
+// 16 loads in flight, into Mpart[g][e].  k_reduce_m adds the groups in order.
+template <typename S>
+__global__ void __launch_bounds__(256) k_msum(Batch<S> bt) {
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done || pb.sc->k == 0) return;
+  const int lb = blockIdx.x - bt.start[req];
+  const int n = mode_of(pb.kb[KB_MSUM], pb.N, lb);
+  const int blk = lb - pb.kb[KB_MSUM][n];
+  const ModeGeom g = pb.g[n];
+  const ModeBufs<S> mb = pb.m[n];
+  const int64_t ne = (int64_t)g.I * g.R;
+  const int tiles = (int)((ne + 63) / 64);
+  const int tile = blk % tiles, q = blk / tiles;
+  const int grp = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int gi = 4 * q + grp;
+  const int64_t e = (int64_t)tile * 64 + l;
+  const int nb = pb.fused_blocks;
+  const int per = (nb + kMsumGroups - 1) / kMsumGroups;
+  const int b0 = gi * per, b1 = min(nb, b0 + per);
+  if (e >= ne) return;
+  double acc = 0.0;
+  constexpr int kU = 16;
+  for (int bb = b0; bb < b1; bb += kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int b = bb + u < b1 ? bb + u : b1 - 1;
+      v[u] = mb.Mq[(int64_t)b * ne + e];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (bb + u < b1) acc += v[u];
+  }
+  mb.Mpart[(int64_t)gi * ne + e] = acc;
+}
+
 // ---------------------------------------------------------------------------
 // Gram S = P P^T in FP64 on the f64 MFMA: lane (p, q) holds P[p][c0+4q .. +3];
 // A[m][k] = P[m][col], B[k][n] = P[n][col] are the same register.
@@ -893,6 +935,10 @@ int gemm_p_blocks(const ModeGeom& g) {
 
 int reduce_m_blocks(const ModeGeom& g) { return (int)(((int64_t)g.I * g.R + 63) / 64); }
 
+int msum_blocks(const ModeGeom& g) {
+  return (int)(((int64_t)g.I * g.R + 63) / 64) * (kMsumGroups / 4);
+}
+
 template <typename S>
 static int mode_grid(const Problem<S>& p, int kind) { return p.kb[kind][p.N]; }
 
@@ -975,8 +1021,24 @@ static void launch_gemm_m_set(const LaunchSet<S>& ls, hipStream_t s) {
 
 template <typename S>
 void launch_gemm_m(const LaunchSet<S>& ls, hipStream_t s) {
-  if (ls.count <= kMaxBatch && !any_wide(ls)) return launch_gemm_m_set(ls, s);
-  for_tile_sets(ls, [s](const LaunchSet<S>& t) { launch_gemm_m_set(t, s); });
+  // problems whose fused pass accumulates every mode's M_n take the first
+  // stage of its reduction instead (never wide: their ranks fit one tile)
+  LaunchSet<S> full, rest;
+  full.count = rest.count = 0;
+  for (int r = 0; r < ls.count; ++r) {
+    LaunchSet<S>& d = ls.host[r]->mfull ? full : rest;
+    d.host[d.count] = ls.host[r];
+    d.dev[d.count] = ls.dev[r];
+    ++d.count;
+  }
+  if (full.count) {
+    Batch<S> b;
+    const int tot = make_batch(full, b, [](const Problem<S>& p) { return mode_grid(p, KB_MSUM); });
+    hipLaunchKernelGGL(k_msum<S>, dim3(tot), dim3(256), 0, s, b);
+  }
+  if (!rest.count) return;
+  if (rest.count <= kMaxBatch && !any_wide(rest)) return launch_gemm_m_set(rest, s);
+  for_tile_sets(rest, [s](const LaunchSet<S>& t) { launch_gemm_m_set(t, s); });
 }
 
 template <typename S>
@@ -1006,17 +1068,6 @@ void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s) {
 // us); at R_n = 10 the MFMA kernel is the faster one (9.7 against 11.4 us at
 // 200^3 FP32).
 // ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_mirror
-constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
-
 template <int NT>
 __device__ __forceinline__ void row_sums(double (&acc)[NT]) {
   double t[NT];

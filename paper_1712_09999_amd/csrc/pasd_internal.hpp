@@ -79,12 +79,18 @@ struct ModeBufs {
   double* Wev;   // RT x RT eigenvectors of the last Gram (warm start)
   double* Fac;   // RT SVT weights f_i of the last eigensolve (f_i > 0: V_n keeps direction i)
   double* Mf;    // merged modes: the fused pass's partials of the next M_n, [fused_blocks][kRT]
+  double* Mq;    // fast modes folded into the fused pass (Problem::mfull): its per-block
+                 // partials of the next M_n, [fused_blocks][I][R]
   int mblocks;   // number of GEMM-M partial blocks
   int sblocks;   // number of Gram partial blocks
 };
 
 // Kernels with a per-mode grid: index into Problem::kb.
-enum ModeKernel { KB_GEMM_M = 0, KB_REDUCE_M, KB_GEMM_P, KB_GRAM, KB_COUNT };
+enum ModeKernel { KB_GEMM_M = 0, KB_REDUCE_M, KB_GEMM_P, KB_GRAM, KB_MSUM, KB_COUNT };
+
+// Groups of fused blocks whose fast-mode partials k_msum sums first; k_reduce_m
+// then adds the group sums (Problem::mfull).
+constexpr int kMsumGroups = 64;
 
 // Everything a kernel needs about one solve.  A device copy lives in the
 // solve's own allocation; kernels reach it through a pointer in Batch.
@@ -131,6 +137,16 @@ struct Problem {
   int mmerge;
   uint32_t mcb;
   int mslab[kMaxN];
+  // mfull (order 4, FP64 state, merged modes 0 and 1): the fused pass also
+  // accumulates the next M_n of the fast modes 2 and 3.  Every chunk of a
+  // thread then has the same last-mode columns i_3 .. i_3 + vec - 1 (the row
+  // length in chunks, Q, divides 256 and mcb, Q <= 64), so the thread keeps
+  // FP64 sums of G_3(x) P_3[:, j_3(x)] for its columns, and a row (one i_2,
+  // Q aligned lanes) sums G_2(x) P_2[:, j_2(x)] across its lanes; each block
+  // writes I_n x R partials to ModeBufs::Mq, k_msum adds them in kMsumGroups
+  // groups of consecutive blocks (in block order) to ModeBufs::Mpart, and
+  // k_reduce_m adds the groups.  GEMM-M runs no mode of such a problem.
+  int mfull;
   // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
   // the rows per mode-n fibre index (B_n / I_N) and I_n
   FastDiv fd_q;
@@ -194,6 +210,18 @@ __device__ __forceinline__ int mode_of(const int* kb, int N, int lblk) {
 
 // Host view of a launch: host copies (for grid sizes and template choices)
 // and device copies (what the kernels dereference) of the same problems.
+// A double moved across lanes by a DPP control (within rows of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_mirror
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
 template <typename S>
 struct LaunchSet {
   int count = 0;
@@ -243,10 +271,11 @@ template <typename S> void launch_mrefresh(const LaunchSet<S>& ls, hipStream_t s
 // tensor of order N with last-mode vector width vec and nchunk = numel / vec
 // chunks, sets *mmerge (0: none), *mcb (chunks per fused block) and *blocks.
 void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank, int state_bytes,
-                bool idx32, int* mmerge, int64_t* mcb, int* blocks);
+                bool idx32, int* mmerge, int64_t* mcb, int* blocks, int* mfull);
 
 // Grid sizes chosen on the host.
 int gemm_m_blocks(const ModeGeom& g, int N);
+int msum_blocks(const ModeGeom& g);
 int gram_blocks(const ModeGeom& g);
 int gemm_p_blocks(const ModeGeom& g);
 int reduce_m_blocks(const ModeGeom& g);

@@ -138,9 +138,9 @@ struct Plan {
   int64_t numel;
   // fused pass: vector width of the last mode, 32-bit offsets, blocks, and
   // the modes whose GEMM-M it folds in (merge_plan)
-  int vec, idx32, fblocks, mmerge;
+  int vec, idx32, fblocks, mmerge, mfull;
   int64_t mcb;
-  size_t off_Mf[kMaxN];
+  size_t off_Mf[kMaxN], off_Mq[kMaxN];
 };
 
 void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
@@ -167,9 +167,11 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
   const int vw = 16 / (int)es;
   p.vec = (c->dims[N - 1] % vw) == 0 ? vw : 1;
   p.idx32 = span * (int64_t)es < (int64_t(1) << 31) ? 1 : 0;
-  merge_plan(c->dims, N, numel, p.vec, rmax, (int)es, p.idx32 != 0, &p.mmerge, &p.mcb, &p.fblocks);
+  merge_plan(c->dims, N, numel, p.vec, rmax, (int)es, p.idx32 != 0, &p.mmerge, &p.mcb, &p.fblocks,
+             &p.mfull);
   for (int n = 0; n < N; ++n) {
-    p.mblocks[n] = n < p.mmerge ? 0 : gemm_m_blocks(p.geom[n], N - p.mmerge);
+    // GEMM-M split-K partials, or with mfull the k_msum group sums
+    p.mblocks[n] = n < p.mmerge ? 0 : p.mfull ? kMsumGroups : gemm_m_blocks(p.geom[n], N - p.mmerge);
     p.sblocks[n] = gram_blocks(p.geom[n]);
   }
   p.off_T = own_T ? p.L.add(numel * es) : 0;  // T read in place when not owned
@@ -194,6 +196,7 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
     p.off_Wev[n] = p.L.add(RT * RT * 8);
     p.off_Fac[n] = p.L.add(RT * 8);
     p.off_Mf[n] = n < p.mmerge ? p.L.add((size_t)p.fblocks * kRT * 8) : 0;
+    p.off_Mq[n] = p.mfull && n >= p.mmerge ? p.L.add((size_t)p.fblocks * g.I * g.R * 8) : 0;
   }
 }
 
@@ -223,6 +226,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     m.Wev = reinterpret_cast<double*>(b + pl.off_Wev[n]);
     m.Fac = reinterpret_cast<double*>(b + pl.off_Fac[n]);
     m.Mf = n < pl.mmerge ? reinterpret_cast<double*>(b + pl.off_Mf[n]) : nullptr;
+    m.Mq = pl.mfull && n >= pl.mmerge ? reinterpret_cast<double*>(b + pl.off_Mq[n]) : nullptr;
     m.mblocks = pl.mblocks[n];
     m.sblocks = pl.sblocks[n];
     p.lam[n] = ctx->lam[n];
@@ -240,7 +244,8 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     for (int k = 0; k < KB_COUNT; ++k) p.kb[k][n] = 0;
   for (int n = 0; n < ctx->N; ++n) {
     const ModeGeom& g = p.g[n];
-    p.kb[KB_GEMM_M][n + 1] = p.kb[KB_GEMM_M][n] + p.m[n].mblocks;
+    p.kb[KB_GEMM_M][n + 1] = p.kb[KB_GEMM_M][n] + (pl.mfull ? 0 : p.m[n].mblocks);
+    p.kb[KB_MSUM][n + 1] = p.kb[KB_MSUM][n] + (pl.mfull && n >= pl.mmerge ? msum_blocks(g) : 0);
     p.kb[KB_REDUCE_M][n + 1] = p.kb[KB_REDUCE_M][n] + reduce_m_blocks(g);
     p.kb[KB_GEMM_P][n + 1] = p.kb[KB_GEMM_P][n] + gemm_p_blocks(g);
     p.kb[KB_GRAM][n + 1] = p.kb[KB_GRAM][n] + p.m[n].sblocks;
@@ -252,6 +257,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   // index divided there, stays below 2^31 bytes
   p.idx32 = pl.idx32;
   p.mmerge = pl.mmerge;
+  p.mfull = pl.mfull;
   p.mcb = (uint32_t)pl.mcb;
   for (int n = 0; n < kMaxN; ++n)
     p.mslab[n] = n < pl.mmerge ? (int)(p.g[n].B / pl.vec / pl.mcb) : 0;
@@ -319,6 +325,7 @@ void fill_views(pasd_ctx* ctx, const Plan& pl, Problem<S>& p, Problem<S>* views)
       v.kb[KB_REDUCE_M][n + 1] = v.kb[KB_REDUCE_M][n] + (has ? reduce_m_blocks(g) : 0);
       v.kb[KB_GEMM_P][n + 1] = v.kb[KB_GEMM_P][n] + (has ? gemm_p_blocks(g) : 0);
       v.kb[KB_GRAM][n + 1] = v.kb[KB_GRAM][n];
+      v.kb[KB_MSUM][n + 1] = v.kb[KB_MSUM][n];
     }
     p.view_host[t] = &v;
     p.view_dev[t] = reinterpret_cast<const Problem<S>*>(dv + (size_t)t * sizeof(Problem<S>));
@@ -465,7 +472,15 @@ void fill_info(pasd_ctx* ctx, pasd_info* info) {
     info->tol_effective = s->tol_eff;
   }
   info->bytes_resident = ctx->bytes;
-  info->merged_modes = ctx->cfg.precision == PASD_FP64 ? ctx->pd.mmerge : ctx->pf.mmerge;
+  // modes whose GEMM-M the fused pass accumulates: 0 .. mmerge-1, and with
+  // mfull every mode
+  if (ctx->cfg.precision == PASD_FP64) {
+    info->merged_modes = ctx->pd.mfull ? ctx->N : ctx->pd.mmerge;
+    info->fused_blocks = ctx->pd.fused_blocks;
+  } else {
+    info->merged_modes = ctx->pf.mfull ? ctx->N : ctx->pf.mmerge;
+    info->fused_blocks = ctx->pf.fused_blocks;
+  }
 }
 
 struct DeviceGuard {

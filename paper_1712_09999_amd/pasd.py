@@ -73,6 +73,7 @@ class Info(ctypes.Structure):
         ("eig_sweeps", ctypes.c_int * MAX_ORDER),
         ("tol_effective", ctypes.c_double),
         ("merged_modes", ctypes.c_int),
+        ("fused_blocks", ctypes.c_int),
     ]
 
 

@@ -206,30 +206,38 @@ def test_checkpoint_restore_is_bitwise():
 # 4-way with a mode-1 slab of 4096 (FP64) or 2048 (FP32) chunks: the fused pass folds in the
 # GEMM-M of modes 0 and 1 (blocks of 1024 chunks, several per slab), with the last mode's
 # columns kept per thread and, in FP64, mode 2's U W rows and the last mode's P columns
-# staged in LDS
+# staged in LDS and the GEMM-M of modes 2 and 3 accumulated too (rows of 64 chunks: lane
+# groups of a whole wave; 16 rows per block, so every block holds a quarter of the i_2 rows)
 MERGED = ((3, 4, 64, 128), (3, 4, 3, 3))
+# (dims, ranks, merged modes in FP64, in FP32)
 MERGED_SHAPES = [
-    MERGED,
-    # FP64 only: rows of 48 chunks (the last mode's columns reloaded per chunk)
-    ((2, 3, 40, 96), (2, 3, 3, 4)),
-    # FP64 only: 300 rows per block, more than the LDS stage holds
-    ((2, 2, 300, 8), (2, 2, 4, 3)),
-    # FP32 rank 10: the largest rank merged with an FP32 state
-    ((2, 3, 64, 64), (2, 3, 10, 10)),
+    (MERGED, 4, 2),
+    # FP64: rows of 48 chunks (the last mode's columns reloaded per chunk, modes 2 and 3
+    # left to GEMM-M); FP32: a slab of 960 chunks, not merged
+    (((2, 3, 40, 96), (2, 3, 3, 4)), 2, 0),
+    # FP64: 300 rows per block, more than the LDS stage holds
+    (((2, 2, 300, 8), (2, 2, 4, 3)), 2, 0),
+    # rank 10: the largest rank merged with an FP32 state; FP64 folds only modes 0 and 1
+    (((2, 3, 64, 64), (2, 3, 10, 10)), 2, 2),
+    # every mode in FP64 at rank 6 (one block per slab, 32 rows), rows of 16 chunks
+    # (lane groups of a quarter wave), and of 8 chunks with 128 rows, the most the stage
+    # holds; in FP32 these slabs hold 512 chunks, not merged
+    (((4, 4, 32, 64), (4, 4, 6, 6)), 4, 0),
+    (((3, 2, 64, 32), (3, 2, 5, 4)), 4, 0),
+    (((2, 2, 128, 16), (2, 2, 6, 5)), 4, 0),
 ]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("dims,ranks", MERGED_SHAPES)
-def test_merged_gemm_m_trajectory(dims, ranks, precision):
+@pytest.mark.parametrize("shape,m64,m32", MERGED_SHAPES)
+def test_merged_gemm_m_trajectory(shape, m64, m32, precision):
+    dims, ranks = shape
     wl = workloads.tucker_workload("merged", dims, tuple(min(r, 3) for r in ranks), 0.1, 17125100,
                                    value_range=(-5, 5), scale="rms")
     T = wl.observed(np.float32 if precision == "fp32" else np.float64).astype(np.float64)
     st = pasd_init(T, ranks, mu0=0.01)
     s = _gpu(T, ranks, precision, mu0=0.01)
-    # the merge plan: FP32 slabs of 40 x 96 and 300 x 8 hold fewer than 1024 chunks
-    fp32_small = precision == "fp32" and dims[2] * dims[3] < 4096
-    assert s.query().merged_modes == (0 if fp32_small else 2), (dims, precision)
+    assert s.query().merged_modes == (m64 if precision == "fp64" else m32), (dims, precision)
     done = 0
     for K in (1, 2, 15, 40):
         pasd_iterate(st, K - done)
@@ -241,14 +249,40 @@ def test_merged_gemm_m_trajectory(dims, ranks, precision):
 def test_merge_plan_limits():
     """Order-4 problems fold GEMM-M of modes 0 and 1 into the fused pass only
     where that was measured faster: slabs of at least 1024 chunks, and ranks up
-    to 10 with an FP32 state (16 with FP64)."""
+    to 10 with an FP32 state (16 with FP64); modes 2 and 3 too with an FP64
+    state up to rank 6."""
     T = np.zeros((2, 3, 64, 64))
-    for prec, R, want in (("fp64", 16, 2), ("fp32", 10, 2), ("fp32", 12, 0)):
+    for prec, R, want in (("fp64", 16, 2), ("fp64", 7, 2), ("fp64", 6, 4), ("fp32", 6, 2),
+                          ("fp32", 10, 2), ("fp32", 12, 0)):
         with P.Solver(T, (2, 3, R, R), precision=prec, tol=0.0, max_iter=10) as s:
             assert s.query().merged_modes == want, (prec, R)
     with P.Solver(np.zeros((32, 48, 40, 56)), (4, 4, 4, 4), precision="fp32", tol=0.0,
                   max_iter=10) as s:
         assert s.query().merged_modes == 0
+
+
+def test_merged_batch_equals_alone():
+    """Problems that fold every mode, two modes and none stepped in one batch
+    give the iterates they give alone, bitwise (each keeps its own kernels,
+    blocks and reduction order)."""
+    specs = [((4, 4, 32, 64), (4, 4, 6, 6)), ((3, 4, 64, 128), (3, 4, 3, 3)),
+             ((2, 3, 64, 64), (2, 3, 10, 10)), ((20, 18, 16), (3, 4, 5))]
+    alone, mixed = [], []
+    for k, (dims, ranks) in enumerate(specs):
+        wl = workloads.tucker_workload("mix", dims, tuple(min(r, 3) for r in ranks), 0.1,
+                                       17125300 + k, value_range=(-5, 5), scale="rms")
+        T = wl.observed(np.float64)
+        a = _gpu(T, ranks, "fp64", mu0=0.01)
+        a.step(23)
+        alone.append(a)
+        mixed.append(_gpu(T, ranks, "fp64", mu0=0.01))
+    assert [m.query().merged_modes for m in mixed] == [4, 4, 2, 0]
+    for _ in range(3):
+        P.step_batch(mixed, 7)
+    P.step_batch(mixed, 2)
+    for a, b in zip(alone, mixed):
+        np.testing.assert_array_equal(a.export(P.Q_D), b.export(P.Q_D))
+        np.testing.assert_array_equal(a.export(P.Q_X), b.export(P.Q_X))
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
