@@ -74,19 +74,22 @@ def kernel_bytes(dims, ranks, es, merged=0, fused_blocks=0):
     gemm_m: reads D and Y_n for every mode it computes   -> 2 (N - merged) numel s, reads
             those P_n (the fused pass accumulates modes 0 .. merged-1 from what it streams);
             with every mode merged that launch is k_msum, which reads the pass's
-            I_n x R_n partials of modes 2 .. N-1 (one per fused block) and writes 64 group
-            sums of each, 8 (fused_blocks + 64) sum I_n R_n bytes
+            I_n x R_n partials of modes 2 .. N-1 (one per fused block, written by the fused
+            pass: 8 fused_blocks sum I_n R_n bytes more there) and writes 64 group sums of
+            each, 8 (fused_blocks + 64) sum I_n R_n bytes
     """
     import math
     N = len(dims)
     numel = math.prod(dims)
     pb = [r * numel // d * es for d, r in zip(dims, ranks)]
+    part = 0  # the fast modes' per-block partials the fused pass writes
     if merged == N:
-        msum = 8 * (fused_blocks + 64) * sum(d * r for d, r in list(zip(dims, ranks))[2:])
+        part = 8 * fused_blocks * sum(d * r for d, r in list(zip(dims, ranks))[2:])
+        msum = part + 8 * 64 * sum(d * r for d, r in list(zip(dims, ranks))[2:])
     else:
         msum = 2 * (N - merged) * numel * es + sum(pb[merged:])
     return {
-        "fused": (2 * N + 2) * numel * es + sum(pb),
+        "fused": (2 * N + 2) * numel * es + sum(pb) + part,
         "gemm_p": 2 * N * numel * es + sum(pb),
         "gemm_m": msum,
     }
