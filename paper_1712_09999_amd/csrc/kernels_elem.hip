@@ -1177,6 +1177,28 @@ static void fused_n(const LaunchSet<S>& ls, hipStream_t s) {
   }
 }
 
+// fused_n per rank class: a problem's reconstruction loads scale with the
+// unrolled rank bound RP, so the problems of a set go out in one launch per
+// class of their own largest rank (a rank-3 solve in a batch with a rank-15
+// one would otherwise run the rank-16 loop).  The padded rank terms are exact
+// zeros, so a problem's results do not depend on the class it launches with.
+template <typename S, int NN, int MM, bool REFRESH = false>
+static void fused_by_rank(const LaunchSet<S>& ls, hipStream_t s) {
+  constexpr int kClasses = 8;
+  LaunchSet<S> cls[kClasses];
+  for (int r = 0; r < ls.count; ++r) {
+    int rm = 1;
+    for (int n = 0; n < ls.host[r]->N; ++n) rm = std::max(rm, ls.host[r]->g[n].R);
+    const int c = NN <= 4 ? std::min(kClasses - 1, (rm - 1) / 2) : std::min(3, (rm - 1) / 4);
+    LaunchSet<S>& d = cls[c];
+    d.host[d.count] = ls.host[r];
+    d.dev[d.count] = ls.dev[r];
+    ++d.count;
+  }
+  for (int c = 0; c < kClasses; ++c)
+    if (cls[c].count) fused_n<S, NN, MM, REFRESH>(cls[c], s);
+}
+
 // Problems of a set by their number of merged modes (0, 1 or 2; 3: every
 // mode, Problem::mfull).  The fast modes' code is compiled for ranks up to 6
 // only, so those problems go out in launches of their own, whose rank bound
@@ -1205,17 +1227,17 @@ void launch_fused(const LaunchSet<S>& ls, hipStream_t s) {
     const int N = nar.host[0]->N;
     if (mg[0].count) {
       switch (N) {
-        case 2: fused_n<S, 2, 0>(mg[0], s); break;
-        case 3: fused_n<S, 3, 0>(mg[0], s); break;
-        case 4: fused_n<S, 4, 0>(mg[0], s); break;
-        case 5: fused_n<S, 5, 0>(mg[0], s); break;
-        case 6: fused_n<S, 6, 0>(mg[0], s); break;
-        case 7: fused_n<S, 7, 0>(mg[0], s); break;
-        default: fused_n<S, 8, 0>(mg[0], s); break;
+        case 2: fused_by_rank<S, 2, 0>(mg[0], s); break;
+        case 3: fused_by_rank<S, 3, 0>(mg[0], s); break;
+        case 4: fused_by_rank<S, 4, 0>(mg[0], s); break;
+        case 5: fused_by_rank<S, 5, 0>(mg[0], s); break;
+        case 6: fused_by_rank<S, 6, 0>(mg[0], s); break;
+        case 7: fused_by_rank<S, 7, 0>(mg[0], s); break;
+        default: fused_by_rank<S, 8, 0>(mg[0], s); break;
       }
     }
-    if (mg[2].count) fused_n<S, 4, 2>(mg[2], s);
-    if (mg[3].count) fused_n<S, 4, 2>(mg[3], s);
+    if (mg[2].count) fused_by_rank<S, 4, 2>(mg[2], s);
+    if (mg[3].count) fused_by_rank<S, 4, 2>(mg[3], s);
   }
   if (wid.count) {
     switch (wid.host[0]->N) {
@@ -1234,8 +1256,8 @@ template <typename S>
 void launch_mrefresh(const LaunchSet<S>& ls, hipStream_t s) {
   LaunchSet<S> mg[4];
   split_merged(ls, mg);
-  if (mg[2].count) fused_n<S, 4, 2, true>(mg[2], s);
-  if (mg[3].count) fused_n<S, 4, 2, true>(mg[3], s);
+  if (mg[2].count) fused_by_rank<S, 4, 2, true>(mg[2], s);
+  if (mg[3].count) fused_by_rank<S, 4, 2, true>(mg[3], s);
 }
 
 template <typename S>
