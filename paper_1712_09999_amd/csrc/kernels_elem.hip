@@ -417,11 +417,33 @@ __device__ __forceinline__ void recon_lds(const S* u_lds, const S (&pv)[RP][VEC]
 // last mode's P columns of the block's rows).
 constexpr int kStageRows = 128;
 
+// x + x(lane ^ D) for D = 16 or 32, the same in both lanes: the gfx950 row
+// swaps (v_permlane16_swap / v_permlane32_swap on two copies of x leave the
+// even and the odd half of each pair of rows, or of the wave, in the two
+// results), added even half first.
+template <int D>
+__device__ __forceinline__ double swap_sum(double x) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)(b & 0xffffffffll), hi = (unsigned)(b >> 32);
+  unsigned l0, l1, h0, h1;
+  if constexpr (D == 16) {
+    const auto L = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto H = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    l0 = L[0], l1 = L[1], h0 = H[0], h1 = H[1];
+  } else {
+    const auto L = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto H = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    l0 = L[0], l1 = L[1], h0 = H[0], h1 = H[1];
+  }
+  return __longlong_as_double(((long long)h0 << 32) | l0) +
+         __longlong_as_double(((long long)h1 << 32) | l1);
+}
+
 // Sum of w over the Q aligned lanes of a row group (Q a power of two, at
 // most 64), left in every lane of the group: DPP exchanges within quads (lanes
 // i^1, i^2), the mirror images within 8 and 16 lanes, then lanes i^16 and
-// i^32.  Every lane adds the same two values at each step (a + b and b + a
-// round alike), so the order is fixed.
+// i^32 by row swaps.  Every lane adds the same two values at each step (a + b
+// and b + a round alike), so the order is fixed.
 template <int NT>
 __device__ __forceinline__ void group_sum(double (&w)[NT], uint32_t Q) {
   double t[NT];
@@ -451,15 +473,11 @@ __device__ __forceinline__ void group_sum(double (&w)[NT], uint32_t Q) {
   }
   if (Q > 16) {
 #pragma unroll
-    for (int e = 0; e < NT; ++e) t[e] = __shfl_xor(w[e], 16, 64);
-#pragma unroll
-    for (int e = 0; e < NT; ++e) w[e] += t[e];
+    for (int e = 0; e < NT; ++e) w[e] = swap_sum<16>(w[e]);
   }
   if (Q > 32) {
 #pragma unroll
-    for (int e = 0; e < NT; ++e) t[e] = __shfl_xor(w[e], 32, 64);
-#pragma unroll
-    for (int e = 0; e < NT; ++e) w[e] += t[e];
+    for (int e = 0; e < NT; ++e) w[e] = swap_sum<32>(w[e]);
   }
 }
 
@@ -490,19 +508,36 @@ __device__ __forceinline__ void fast_acc(double (&acc3)[VEC][RP], double (&w)[RP
 }
 
 // Block end of the fast modes (Problem::mfull; blockDim = 256): the block's
-// I_2 x R partial of M_2 (its rows' sums m2[k][r] for i_2 = i2a + k, k <
-// nrows, zero elsewhere) and I_3 x R partial of M_3 (for column i_3 = VEC cq
-// + t, the sum over the threads cq, cq + Q, ... of their acc3[t], in thread
-// order) to Mq[lblk].
+// I_2 x R_2 partial of M_2 (its rows' sums m2[k][r] for i_2 = i2a + k, k <
+// nrows, zero elsewhere) and I_3 x R_3 partial of M_3, which holds for column
+// i_3 = VEC cq + t the sum over the threads cq, cq + Q, ... of their acc3[t]:
+// first within each wave by lane butterflies over the lanes of equal column
+// (xor Q, 2Q, ... below 64), then over the four waves in order.  (Writing each
+// row's sums to global memory from inside the sweep was measured slower: the
+// stores hold up the waits for the next chunk's loads.)
 template <typename S, int NN, int VEC, int RP>
-__device__ __forceinline__ void fast_store(const Problem<S>& pb, int lblk,
-                                           const double (&acc3)[VEC][RP], const double* m2,
-                                           uint32_t i2a, uint32_t nrows, uint32_t Q) {
-  __shared__ double st_a3[256][VEC * RP];
+__device__ __forceinline__ void fast_store(const Problem<S>& pb, int lblk, double (&acc3)[VEC][RP],
+                                           const double* m2, uint32_t i2a, uint32_t nrows,
+                                           uint32_t Q) {
+  constexpr int NV = VEC * RP;
+  __shared__ double red3[4][64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (uint32_t o = Q; o < 64; o <<= 1) {
 #pragma unroll
-  for (int t = 0; t < VEC; ++t)
+    for (int t = 0; t < VEC; ++t)
 #pragma unroll
-    for (int r = 0; r < RP; ++r) st_a3[threadIdx.x][t * RP + r] = acc3[t][r];
+      for (int r = 0; r < RP; ++r) {
+        const double x = acc3[t][r];
+        acc3[t][r] = o == 16 ? swap_sum<16>(x) : o == 32 ? swap_sum<32>(x)
+                                               : x + __shfl_xor(x, (int)o, 64);
+      }
+  }
+  if ((uint32_t)lane < Q) {
+#pragma unroll
+    for (int t = 0; t < VEC; ++t)
+#pragma unroll
+      for (int r = 0; r < RP; ++r) red3[wave][lane][t * RP + r] = acc3[t][r];
+  }
   __syncthreads();
   {
     const int R2 = pb.g[NN - 2].R;
@@ -513,18 +548,16 @@ __device__ __forceinline__ void fast_store(const Problem<S>& pb, int lblk,
       q2[e] = (i2 >= i2a && i2 - i2a < nrows) ? m2[(i2 - i2a) * RP + r] : 0.0;
     }
   }
-  {
-    const int R3 = pb.g[NN - 1].R;
-    const uint32_t ne = (uint32_t)pb.g[NN - 1].I * R3;
-    double* q3 = pb.m[NN - 1].Mq + (int64_t)lblk * ne;
-    const uint32_t nm = blockDim.x / Q;
-    for (uint32_t e = threadIdx.x; e < ne; e += blockDim.x) {
-      const uint32_t i3 = e / R3, r = e - i3 * R3;
-      const uint32_t cq = i3 / VEC, t = i3 - cq * VEC;
-      double sum = 0.0;
-      for (uint32_t m = 0; m < nm; ++m) sum += st_a3[cq + Q * m][t * RP + r];
-      q3[e] = sum;
-    }
+  const int R3 = pb.g[NN - 1].R;
+  double* q3 = pb.m[NN - 1].Mq + (int64_t)lblk * pb.g[NN - 1].I * R3;
+  for (uint32_t e = threadIdx.x; e < Q * NV; e += blockDim.x) {
+    const uint32_t cq = e / NV, k = e - cq * NV;
+    const uint32_t t = k / RP, r = k - t * RP;
+    if ((int)r >= R3) continue;
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) sum += red3[w][cq][k];  // every wave holds one sum per column
+    q3[(cq * VEC + t) * R3 + r] = sum;
   }
 }
 
@@ -593,8 +626,9 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
   // 364 -> 447 us) and they are loaded per chunk
   constexpr bool kHoistP2 = kStage && RP != 8;
   S p2k[kHoistP2 ? RPk : 1][VEC];
-  // the fast modes' GEMM-M in the pass (Problem::mfull, ranks up to 6)
-  constexpr bool kFull = kHoistP2 && RP <= 6;
+  // the fast modes' GEMM-M in the pass (Problem::mfull, ranks up to 6, the
+  // 16-byte vector path)
+  constexpr bool kFull = kHoistP2 && RP <= 6 && VEC == VW<S>::n;
   bool mfull = false;
   double acc3[kFull ? VEC : 1][kFull ? RPk : 1];
   __shared__ double st_m2[kFull ? kStageRows : 1][kFull ? RPk : 1];
@@ -845,7 +879,7 @@ __device__ __forceinline__ void mrefresh_body(const Problem<S>& pb, int lblk) {
     for (int r = 0; r < RP; ++r) macc[n][r] = 0.0;
   const IT c0 = (IT)lblk * (IT)pb.mcb, c1 = c0 + (IT)pb.mcb;
   // the fast modes (Problem::mfull): the pass's P_2 columns, sums and order
-  constexpr bool kFull = sizeof(S) == 8 && NN == 4 && RP <= 6;
+  constexpr bool kFull = sizeof(S) == 8 && NN == 4 && RP <= 6 && VEC == VW<S>::n;
   const bool mfull = kFull && pb.mfull;
   double acc3[kFull ? VEC : 1][kFull ? RP : 1];
   S p2k[kFull ? RP : 1][VEC];
@@ -1096,11 +1130,13 @@ void merge_plan(const int64_t* dims, int N, int64_t numel, int vec, int max_rank
     *mmerge = d + 1;
     *mcb = cb;
     *blocks = (int)nb;
-    // the fast modes too (FP64, ranks up to 6) when every chunk of a thread
-    // has the same last-mode columns (Q | 256 and Q | mcb), a row group lies
-    // in one wave (Q <= 64) and the block's rows fit the LDS stage
+    // the fast modes too (FP64, ranks up to 6, the 16-byte vector path) when
+    // every chunk of a thread has the same last-mode columns (Q | 256 and Q |
+    // mcb), a row group lies in one wave (Q <= 64) and the block's rows fit
+    // the LDS stage
     const int64_t Q = dims[N - 1] / vec;
-    *mfull = state_bytes == 8 && max_rank <= 6 && Q <= 64 && 256 % Q == 0 && cb % Q == 0 &&
+    *mfull = state_bytes == 8 && vec == 2 && max_rank <= 6 && Q <= 64 && 256 % Q == 0 &&
+             cb % Q == 0 &&
              cb / Q <= kStageRows;
     return;
   }
