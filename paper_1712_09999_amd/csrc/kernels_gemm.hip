@@ -617,6 +617,34 @@ __global__ void __launch_bounds__(512) k_gemm_m(Batch<S> bt) {
   }
 }
 
+// A mode whose GEMM-M the fused pass folds in (n < Problem::mmerge): M[i][r]
+// is the sum over the fused blocks of every slab with index i, blocks
+// (a I + i) K + k for term t = a K + k (a < A, k < K = mslab[n]); thread group
+// grp sums the terms grp, grp + 4, ... of entry e = i R + r into
+// acc[(t / 4) % 4], 16 loads in flight.
+template <typename S>
+__device__ __forceinline__ void merged_terms(const Problem<S>& pb, int n, int64_t e, int grp,
+                                             double (&acc)[4]) {
+  const ModeGeom g = pb.g[n];
+  if (e >= (int64_t)g.I * g.R) return;
+  const double* Mf = pb.m[n].Mf;
+  const int64_t i = e / g.R, r = e - i * g.R;
+  const int64_t K = pb.mslab[n], nt = g.A * K;
+  constexpr int kRM = 16;
+  for (int64_t t0 = grp; t0 < nt; t0 += 4 * kRM) {
+    double v[kRM];
+#pragma unroll
+    for (int u = 0; u < kRM; ++u) {
+      const int64_t t = t0 + 4 * u < nt ? t0 + 4 * u : nt - 1;
+      const int64_t a = t / K, k = t - a * K;
+      v[u] = Mf[((a * g.I + i) * K + k) * kRT + r];
+    }
+#pragma unroll
+    for (int u = 0; u < kRM; ++u)
+      if (t0 + 4 * u < nt) acc[u % 4] += v[u];
+  }
+}
+
 // Fixed-order reduction of the GEMM-M partials: M[i][r] = sum_blk Mpart[blk][i][r]
 // (partials I x R, the reduced M in rows of kRT whose columns >= R are unused).
 // A block owns 64 consecutive entries; its 4 thread groups sum interleaved
@@ -636,27 +664,7 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   __shared__ double part[4][64];
   double acc[4] = {0, 0, 0, 0};
   if (n < pb.mmerge) {
-    // a mode whose GEMM-M the fused pass folds in: M[i][r] is the sum over
-    // the fused blocks of every slab with index i, blocks (a I + i) K + k for
-    // term t = a K + k (a < A, k < K = mslab[n]); group grp sums the terms
-    // grp, grp + 4, ... into acc[(t / 4) % 4], as below
-    if (e < ne) {
-      const int64_t i = e / g.R, r = e - i * g.R;
-      const int64_t K = pb.mslab[n], nt = g.A * K;
-      constexpr int kRM = 16;
-      for (int64_t t0 = grp; t0 < nt; t0 += 4 * kRM) {
-        double v[kRM];
-#pragma unroll
-        for (int u = 0; u < kRM; ++u) {
-          const int64_t t = t0 + 4 * u < nt ? t0 + 4 * u : nt - 1;
-          const int64_t a = t / K, k = t - a * K;
-          v[u] = mb.Mf[((a * g.I + i) * K + k) * kRT + r];
-        }
-#pragma unroll
-        for (int u = 0; u < kRM; ++u)
-          if (t0 + 4 * u < nt) acc[u % 4] += v[u];
-      }
-    }
+    merged_terms<S>(pb, n, e, grp, acc);
   } else if (e < ne) {
     // group grp sums partials grp, grp + 4, ... into acc[(b / 4) % 4]; kRM
     // unconditional loads per pass (index clamped, value masked) are in
@@ -684,12 +692,20 @@ __global__ void __launch_bounds__(256) k_reduce_m(Batch<S> bt) {
   }
 }
 
-// First stage of the fast modes' GEMM-M reduction when the fused pass
-// accumulates them (Problem::mfull): the pass leaves one I_n x R partial per
-// block in Mq; block (tile, q) of mode n takes the 64 entries e = 64 tile +
-// lane, and its thread group grp the fused blocks of group g = 4 q + grp (the
-// g-th of kMsumGroups runs of consecutive blocks), summed in block order with
-// 16 loads in flight, into Mpart[g][e].  k_reduce_m adds the groups in order.
+// The GEMM-M reduction of a problem whose fused pass accumulates every mode
+// (Problem::mfull), in place of GEMM-M and k_reduce_m.  A merged mode's block
+// adds its 64 entries' slab sums as k_reduce_m does.  For the fast modes the
+// pass leaves one I_n x R partial per block in Mq; block (tile, q) of mode n
+// takes the 64 entries e = 64 tile + lane, and its thread group grp the fused
+// blocks of group g = 4 q + grp (the g-th of kMsumGroups runs of consecutive
+// blocks), summed in block order with 16 loads in flight, into Mpart[g][e].
+// The last of the tile's blocks to finish adds the kMsumGroups group sums in a
+// fixed order into M (group grp the groups grp, grp + 4, ..., then the four in
+// order).  The group sums, the count and the last block's reads are
+// device-scope accesses, coherent across XCDs without a cache write-back, and
+// a block's group sums are written (vmcnt(0)) before the barrier after which
+// it counts itself.  (With a __threadfence() before each block counts itself
+// this kernel took 37 us instead of 13 us.)
 template <typename S>
 __global__ void __launch_bounds__(256) k_msum(Batch<S> bt) {
   const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
@@ -701,29 +717,71 @@ __global__ void __launch_bounds__(256) k_msum(Batch<S> bt) {
   const ModeGeom g = pb.g[n];
   const ModeBufs<S> mb = pb.m[n];
   const int64_t ne = (int64_t)g.I * g.R;
+  const int grp = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __shared__ double part[4][64];
+  __shared__ int last;
+  if (n < pb.mmerge) {
+    const int64_t e = (int64_t)blk * 64 + l;
+    double acc[4] = {0, 0, 0, 0};
+    merged_terms<S>(pb, n, e, grp, acc);
+    part[grp][l] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (grp == 0 && e < ne) {
+      const int64_t i = e / g.R;
+      mb.M[i * kRT + (e - i * g.R)] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+    }
+    return;
+  }
   const int tiles = (int)((ne + 63) / 64);
   const int tile = blk % tiles, q = blk / tiles;
-  const int grp = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int gi = 4 * q + grp;
   const int64_t e = (int64_t)tile * 64 + l;
   const int nb = pb.fused_blocks;
   const int per = (nb + kMsumGroups - 1) / kMsumGroups;
   const int b0 = gi * per, b1 = min(nb, b0 + per);
-  if (e >= ne) return;
-  double acc = 0.0;
   constexpr int kU = 16;
-  for (int bb = b0; bb < b1; bb += kU) {
-    double v[kU];
+  if (e < ne) {
+    double acc = 0.0;
+    for (int bb = b0; bb < b1; bb += kU) {
+      double v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int b = bb + u < b1 ? bb + u : b1 - 1;
-      v[u] = mb.Mq[(int64_t)b * ne + e];
+      for (int u = 0; u < kU; ++u) {
+        const int b = bb + u < b1 ? bb + u : b1 - 1;
+        v[u] = mb.Mq[(int64_t)b * ne + e];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (bb + u < b1) acc += v[u];
     }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (bb + u < b1) acc += v[u];
+    __hip_atomic_store(&mb.Mpart[(int64_t)gi * ne + e], acc, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
   }
-  mb.Mpart[(int64_t)gi * ne + e] = acc;
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this thread's group sum is written
+  __syncthreads();
+  if (threadIdx.x == 0)
+    last = __hip_atomic_fetch_add(&mb.mcnt[tile], 1u, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == (unsigned)(kMsumGroups / 4 - 1);
+  __syncthreads();
+  if (!last) return;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&mb.mcnt[tile], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double acc = 0.0;
+  if (e < ne) {
+    constexpr int kG = kMsumGroups / 4;
+    double v[kG];
+#pragma unroll
+    for (int u = 0; u < kG; ++u)
+      v[u] = __hip_atomic_load(&mb.Mpart[(int64_t)(grp + 4 * u) * ne + e], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int u = 0; u < kG; ++u) acc += v[u];
+  }
+  part[grp][l] = acc;
+  __syncthreads();
+  if (grp == 0 && e < ne) {
+    const int64_t i = e / g.R;
+    mb.M[i * kRT + (e - i * g.R)] = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,8 +1108,18 @@ static void launch_reduce_m_set(const LaunchSet<S>& ls, hipStream_t s) {
 
 template <typename S>
 void launch_reduce_m(const LaunchSet<S>& ls, hipStream_t s) {
-  if (ls.count <= kMaxBatch && !any_wide(ls)) return launch_reduce_m_set(ls, s);
-  for_tile_sets(ls, [s](const LaunchSet<S>& t) { launch_reduce_m_set(t, s); });
+  // k_msum has reduced every mode of the problems that fold them all
+  LaunchSet<S> rest;
+  rest.count = 0;
+  for (int r = 0; r < ls.count; ++r) {
+    if (ls.host[r]->mfull) continue;
+    rest.host[rest.count] = ls.host[r];
+    rest.dev[rest.count] = ls.dev[r];
+    ++rest.count;
+  }
+  if (!rest.count) return;
+  if (rest.count <= kMaxBatch && !any_wide(rest)) return launch_reduce_m_set(rest, s);
+  for_tile_sets(rest, [s](const LaunchSet<S>& t) { launch_reduce_m_set(t, s); });
 }
 
 // ---------------------------------------------------------------------------

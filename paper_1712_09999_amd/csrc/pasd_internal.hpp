@@ -81,6 +81,7 @@ struct ModeBufs {
   double* Mf;    // merged modes: the fused pass's partials of the next M_n, [fused_blocks][kRT]
   double* Mq;    // fast modes folded into the fused pass (Problem::mfull): its per-block
                  // partials of the next M_n, [fused_blocks][I][R]
+  unsigned int* mcnt;  // with Mq: per 64-entry tile of M_n, the k_msum blocks done (0 between launches)
   int mblocks;   // number of GEMM-M partial blocks
   int sblocks;   // number of Gram partial blocks
 };
@@ -144,8 +145,10 @@ struct Problem {
   // FP64 sums of G_3(x) P_3[:, j_3(x)] for its columns, and a row (one i_2,
   // Q aligned lanes) sums G_2(x) P_2[:, j_2(x)] across its lanes; each block
   // writes I_n x R partials to ModeBufs::Mq, k_msum adds them in kMsumGroups
-  // groups of consecutive blocks (in block order) to ModeBufs::Mpart, and
-  // k_reduce_m adds the groups.  GEMM-M runs no mode of such a problem.
+  // groups of consecutive blocks (in block order) to ModeBufs::Mpart and the
+  // last of a tile's blocks adds the groups into M_n; k_msum also reduces the
+  // merged modes' slab sums.  Neither GEMM-M nor k_reduce_m runs for such a
+  // problem.
   int mfull;
   // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
   // the rows per mode-n fibre index (B_n / I_N) and I_n

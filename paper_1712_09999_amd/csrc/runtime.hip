@@ -140,7 +140,7 @@ struct Plan {
   // the modes whose GEMM-M it folds in (merge_plan)
   int vec, idx32, fblocks, mmerge, mfull;
   int64_t mcb;
-  size_t off_Mf[kMaxN], off_Mq[kMaxN];
+  size_t off_Mf[kMaxN], off_Mq[kMaxN], off_mcnt[kMaxN];
 };
 
 void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
@@ -197,6 +197,7 @@ void make_plan(const pasd_config* c, Plan& p, bool own_T = true) {
     p.off_Fac[n] = p.L.add(RT * 8);
     p.off_Mf[n] = n < p.mmerge ? p.L.add((size_t)p.fblocks * kRT * 8) : 0;
     p.off_Mq[n] = p.mfull && n >= p.mmerge ? p.L.add((size_t)p.fblocks * g.I * g.R * 8) : 0;
+    p.off_mcnt[n] = p.mfull && n >= p.mmerge ? p.L.add(((size_t)g.I * g.R + 63) / 64 * 4) : 0;
   }
 }
 
@@ -227,6 +228,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
     m.Fac = reinterpret_cast<double*>(b + pl.off_Fac[n]);
     m.Mf = n < pl.mmerge ? reinterpret_cast<double*>(b + pl.off_Mf[n]) : nullptr;
     m.Mq = pl.mfull && n >= pl.mmerge ? reinterpret_cast<double*>(b + pl.off_Mq[n]) : nullptr;
+    m.mcnt = pl.mfull && n >= pl.mmerge ? reinterpret_cast<unsigned int*>(b + pl.off_mcnt[n]) : nullptr;
     m.mblocks = pl.mblocks[n];
     m.sblocks = pl.sblocks[n];
     p.lam[n] = ctx->lam[n];
@@ -245,7 +247,8 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   for (int n = 0; n < ctx->N; ++n) {
     const ModeGeom& g = p.g[n];
     p.kb[KB_GEMM_M][n + 1] = p.kb[KB_GEMM_M][n] + (pl.mfull ? 0 : p.m[n].mblocks);
-    p.kb[KB_MSUM][n + 1] = p.kb[KB_MSUM][n] + (pl.mfull && n >= pl.mmerge ? msum_blocks(g) : 0);
+    p.kb[KB_MSUM][n + 1] = p.kb[KB_MSUM][n] +
+                           (!pl.mfull ? 0 : n >= pl.mmerge ? msum_blocks(g) : reduce_m_blocks(g));
     p.kb[KB_REDUCE_M][n + 1] = p.kb[KB_REDUCE_M][n] + reduce_m_blocks(g);
     p.kb[KB_GEMM_P][n + 1] = p.kb[KB_GEMM_P][n] + gemm_p_blocks(g);
     p.kb[KB_GRAM][n + 1] = p.kb[KB_GRAM][n] + p.m[n].sblocks;
