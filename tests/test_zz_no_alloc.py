@@ -1,7 +1,9 @@
 """pasd_solve_static, the entry point that allocates nothing (its state lives
 in the library's static device array), against the allocating path
 pasd_create + pasd_solve + pasd_get_result on the same inputs: two calls in a
-row, the second with a smaller tensor, in FP64 and FP32, plus the size limit.
+row, the second with a smaller tensor, in FP64 and FP32 (3-way) and for order-4
+FP64 tensors whose fused pass folds in every mode's GEMM-M, plus the size
+limit.
 
 Both paths run the same kernels in the same order (the allocating one with
 PASD_FLAG_NO_GRAPH here, so both launch directly), so iteration counts,
@@ -67,6 +69,14 @@ def test_static_solve_matches_allocating_solve_twice(precision):
     # first call, then a smaller one that reuses the same static array
     _case((40, 36, 32), (4, 4, 3), 11, precision)
     _case((24, 20, 18), (3, 3, 2), 12, precision)
+
+
+def test_static_solve_folded_order4_twice():
+    # order 4, FP64, ranks up to 6: the fused pass accumulates every mode's
+    # GEMM-M, with its per-block partials and tile counters in the static
+    # array too; the second call is smaller
+    _case((4, 4, 32, 64), (4, 4, 6, 6), 13, "fp64")
+    _case((3, 2, 64, 32), (3, 2, 5, 4), 14, "fp64")
 
 
 def test_static_solve_rejects_state_above_the_array():
