@@ -65,12 +65,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
 
 
-def kernel_bytes(dims, ranks, es, merged=0, fused_blocks=0):
+def kernel_bytes(dims, ranks, es, merged=0, fused_blocks=0, pair=0):
     """Algorithmic HBM bytes per launch of the streaming kernels.
 
     fused : reads T and Y_1..Y_N, writes D and Y_1..Y_N  -> (2N + 2) numel s
             plus one read of every P_n (R_n J_n s)
-    gemm_p: reads D and Y_n for every mode               -> 2 N numel s, writes P_n
+    gemm_p: reads D and Y_n for every mode               -> 2 N numel s, writes P_n;
+            with `pair` the last two modes share one read of D -> (2 N - 1) numel s
     gemm_m: reads D and Y_n for every mode it computes   -> 2 (N - merged) numel s, reads
             those P_n (the fused pass accumulates modes 0 .. merged-1 from what it streams);
             with every mode merged that launch is k_msum, which reads the pass's
@@ -90,7 +91,7 @@ def kernel_bytes(dims, ranks, es, merged=0, fused_blocks=0):
         msum = 2 * (N - merged) * numel * es + sum(pb[merged:])
     return {
         "fused": (2 * N + 2) * numel * es + sum(pb) + part,
-        "gemm_p": 2 * N * numel * es + sum(pb),
+        "gemm_p": (2 * N - (1 if pair else 0)) * numel * es + sum(pb),
         "gemm_m": msum,
     }
 
@@ -375,7 +376,7 @@ def _timed_iterations(T, ranks, prec, steps, warmup):
     info = s.query()
     s.close()
     return (ms, {k: {"ms": t / max(c, 1)} for k, (t, c) in prof.items()},
-            (info.merged_modes, info.fused_blocks))
+            (info.merged_modes, info.fused_blocks, info.gemm_p_pair))
 
 
 def cpu_info():
@@ -445,8 +446,8 @@ def main():
                                                      hprec, args.steps, args.warmup)
     value = 1000.0 / ms_per_step
     _progress(f"{args.workload} {hprec}: timed {args.steps} iterations: {ms_per_step:.4f} ms each")
-    merged, fused_blocks = merged
-    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4, merged, fused_blocks)
+    merged, fused_blocks, pair = merged
+    kb = kernel_bytes(dims, ranks, 8 if hprec == "fp64" else 4, merged, fused_blocks, pair)
     for k, b in kb.items():
         kernels[k]["alg_bytes"] = b
         kernels[k]["GB/s"] = b / (kernels[k]["ms"] * 1e-3) / 1e9
@@ -481,6 +482,7 @@ def main():
         "roofline": roofline,
         "kernel_sum_ms": round(ksum, 5),
         "merged_modes": merged,
+        "gemm_p_pair": pair,
         "iteration_alg_bytes": int(sum(kb.values())),
         "iteration_alg_GBps": round(sum(kb.values()) / (ms_per_step * 1e-3) / 1e9, 1),
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

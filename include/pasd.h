@@ -134,6 +134,10 @@ typedef struct {
                                        states up to rank 10) or 4 (also the last two modes: FP64
                                        state, ranks up to 6, rows of at most 64 vectors) */
   int fused_blocks;                 /* workgroups of one launch of the fused pass */
+  int gemm_p_pair;                  /* 1: P_n = U_n^T G_n (eq. (13)) of the last two modes
+                                       runs as one pass over their 64 x 64 slabs, reading
+                                       D = T - E once for both (order >= 3, I_{N-2} = I_{N-1}
+                                       = 64, every R_n <= 16, not with split-BF16 operands) */
 } pasd_info;
 
 typedef struct pasd_ctx pasd_ctx;

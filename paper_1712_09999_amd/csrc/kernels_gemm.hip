@@ -150,6 +150,108 @@ __device__ __forceinline__ void load_g4(const S* __restrict__ D, const S* __rest
 // one tile since they share the output.
 // ---------------------------------------------------------------------------
 
+// Orders the LDS accesses of one wave: the compiler keeps them on their side
+// of this point, and the LDS executes a wave's accesses in issue order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// GEMM-P of the last two modes together (Problem::gp2: I_{N-2} = I_{N-1} =
+// 64).  The 64 x 64 slab of index a over modes 0 .. N-3 holds tile a of both
+// unfoldings: columns 64 a .. 64 a + 63 of mode N-2 (contraction over
+// i_{N-2}) and rows 64 a .. 64 a + 63 of mode N-1 (contraction over
+// i_{N-1}).  One block reads D there once for both modes, and Y_{N-2},
+// Y_{N-1} once each, instead of D twice.  Wave w takes rows i_{N-2} = 16 w ..
+// 16 w + 15: for mode N-2 the column scheme's fragments (lane (p, q): rows
+// 16 w + 4 k + q, columns 4 p .. 4 p + 3) and its LDS sum over the waves, for
+// mode N-1 the row scheme's (row 16 w + p, columns 16 k + 4 q .. + 3), with D
+// brought into them by a transpose through the wave's own LDS region.  Both
+// modes' products and sums run in the one-mode kernel's order, so P_n is
+// bitwise the same as there.
+// (At most 168 registers, three waves per SIMD: FP64 fits without spilling,
+// 208 -> 202 us for the GEMM-P of 64^4 against two waves.)
+template <typename S, bool BF>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_gemm_p2(Batch<S> bt) {
+  typedef typename MM<S>::acc_t Acc;
+  typedef typename MM<S>::vec_t V;
+  const int req = batch_find(bt.start, bt.nreq, blockIdx.x);
+  const Problem<S>& pb = *bt.p[req];
+  if (pb.sc->done) return;
+  const int64_t a = blockIdx.x - bt.start[req];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int p = lane & 15, q = lane >> 4;
+  const int n2 = pb.N - 2, n3 = pb.N - 1;
+  const ModeGeom g2 = pb.g[n2], g3 = pb.g[n3];
+  const ModeBufs<S> m2 = pb.m[n2], m3 = pb.m[n3];
+  const S inv_mu = S(1.0 / pb.sc->mu);
+  // per wave 1024 elements: first the transposed 16 x 64 rows of D (4-element
+  // groups of row r at group index g ^ (r & 15)), then the wave's sums
+  __shared__ __align__(32) S red[4][64][16];
+  S* buf = &red[wave][0][0];
+  const int64_t base = a * 4096;
+  V d[4], y2[4], y3[4];
+  S u2[4], u3[4][4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int row = 16 * wave + 4 * k + q;
+    d[k] = *reinterpret_cast<const V*>(pb.D + base + row * 64 + 4 * p);
+    y2[k] = *reinterpret_cast<const V*>(m2.Y + base + row * 64 + 4 * p);
+    u2[k] = m2.Us[row * kRT + p];
+    y3[k] = *reinterpret_cast<const V*>(m3.Y + base + (16 * wave + p) * 64 + 16 * k + 4 * q);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) u3[k][t] = m3.Us[(16 * k + 4 * q + t) * kRT + p];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  Acc acc2[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc2[t] = Acc{0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc2[t] = mma_op<BF, S>(u2[k], d[k][t] + y2[k][t] * inv_mu, acc2[t]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = 4 * k + q;
+    *reinterpret_cast<V*>(buf + r * 64 + 4 * (p ^ r)) = d[k];
+  }
+  wave_lds_sync();
+  Acc acc3 = Acc{0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const V d3 = *reinterpret_cast<const V*>(buf + p * 64 + 4 * ((4 * k + q) ^ p));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc3 = mma_op<BF, S>(d3[t] + y3[k][t] * inv_mu, u3[k][t], acc3);
+  }
+  // acc3[v] = P_{N-1}[p][64 a + 16 w + row(q, v)]
+  if (p < g3.R) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      m3.P[(int64_t)p * g3.J + a * 64 + 16 * wave + MM<S>::row(q, v)] = acc3[v];
+  }
+  wave_lds_sync();  // the transposed rows are read out before the sums overwrite them
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[wave][lane][t * 4 + v] = acc2[t][v];
+  __syncthreads();
+  if (wave == 0) {
+    // P_{N-2}[r][64 a + 4 p + t], r = row(q, v), in the column scheme's order
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = MM<S>::row(q, v);
+      if (r >= g2.R) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        S s = red[0][lane][t * 4 + v] + red[1][lane][t * 4 + v] + red[2][lane][t * 4 + v] +
+              red[3][lane][t * 4 + v];
+        m2.P[(int64_t)r * g2.J + a * 64 + 4 * p + t] = s;
+      }
+    }
+  }
+}
+
 template <typename S, bool BF>
 __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
   typedef typename MM<S>::acc_t Acc;
@@ -1034,13 +1136,25 @@ template <typename S>
 static void launch_gemm_p_set(const LaunchSet<S>& ls, hipStream_t s) {
   Batch<S> b;
   const int tot = make_batch(ls, b, [](const Problem<S>& p) { return mode_grid(p, KB_GEMM_P); });
+  LaunchSet<S> pair;
+  pair.count = 0;
+  for (int r = 0; r < ls.count; ++r)
+    if (ls.host[r]->gp2) {
+      pair.host[pair.count] = ls.host[r];
+      pair.dev[pair.count] = ls.dev[r];
+      ++pair.count;
+    }
+  Batch<S> b2;
+  const int tot2 = pair.count ? make_batch(pair, b2, [](const Problem<S>& p) { return p.gp2; }) : 0;
   if constexpr (sizeof(S) == 4) {
     if (bf16_set(ls)) {
-      hipLaunchKernelGGL((k_gemm_p<S, true>), dim3(tot), dim3(256), 0, s, b);
+      if (tot) hipLaunchKernelGGL((k_gemm_p<S, true>), dim3(tot), dim3(256), 0, s, b);
+      if (tot2) hipLaunchKernelGGL((k_gemm_p2<S, true>), dim3(tot2), dim3(256), 0, s, b2);
       return;
     }
   }
-  hipLaunchKernelGGL((k_gemm_p<S, false>), dim3(tot), dim3(256), 0, s, b);
+  if (tot) hipLaunchKernelGGL((k_gemm_p<S, false>), dim3(tot), dim3(256), 0, s, b);
+  if (tot2) hipLaunchKernelGGL((k_gemm_p2<S, false>), dim3(tot2), dim3(256), 0, s, b2);
 }
 
 template <typename S>

@@ -150,6 +150,10 @@ struct Problem {
   // merged modes' slab sums.  Neither GEMM-M nor k_reduce_m runs for such a
   // problem.
   int mfull;
+  // GEMM-P blocks of the last two modes taken together (k_gemm_p2; every
+  // R_n <= kRT, I_{N-2} = I_{N-1} = 64, N >= 3): one per 64 x 64 slab, 0
+  // otherwise; those modes then have no blocks of their own in kb[KB_GEMM_P]
+  int gp2;
   // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
   // the rows per mode-n fibre index (B_n / I_N) and I_n
   FastDiv fd_q;

@@ -244,13 +244,25 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   // per-mode block offsets of the mode-grouped kernels, and the fused-pass share
   for (int n = 0; n <= ctx->N; ++n)
     for (int k = 0; k < KB_COUNT; ++k) p.kb[k][n] = 0;
+  {
+    // GEMM-P of the last two modes as one pass over their 64 x 64 slabs
+    const int N = ctx->N;
+    bool narrow = true;
+    for (int n = 0; n < N; ++n) narrow = narrow && p.g[n].R <= kRT;
+    // (not with split-BF16 operands: the splitting doubles the pass's
+    // registers, and there it was measured slower, 135 -> 142 us at 64^4)
+    p.gp2 = (N >= 3 && narrow && p.g[N - 1].I == 64 && p.g[N - 2].I == 64 &&
+             p.precision != PASD_BF16_GEMM)
+                ? (int)p.g[N - 2].A
+                : 0;
+  }
   for (int n = 0; n < ctx->N; ++n) {
     const ModeGeom& g = p.g[n];
     p.kb[KB_GEMM_M][n + 1] = p.kb[KB_GEMM_M][n] + (pl.mfull ? 0 : p.m[n].mblocks);
     p.kb[KB_MSUM][n + 1] = p.kb[KB_MSUM][n] +
                            (!pl.mfull ? 0 : n >= pl.mmerge ? msum_blocks(g) : reduce_m_blocks(g));
     p.kb[KB_REDUCE_M][n + 1] = p.kb[KB_REDUCE_M][n] + reduce_m_blocks(g);
-    p.kb[KB_GEMM_P][n + 1] = p.kb[KB_GEMM_P][n] + gemm_p_blocks(g);
+    p.kb[KB_GEMM_P][n + 1] = p.kb[KB_GEMM_P][n] + (p.gp2 && n >= ctx->N - 2 ? 0 : gemm_p_blocks(g));
     p.kb[KB_GRAM][n + 1] = p.kb[KB_GRAM][n] + p.m[n].sblocks;
   }
   const int vw = 16 / (int)sizeof(S);
@@ -306,6 +318,7 @@ void fill_views(pasd_ctx* ctx, const Plan& pl, Problem<S>& p, Problem<S>* views)
     v = p;
     v.wide = 0;
     v.ntiles = 1;
+    v.gp2 = 0;
     for (int u = 0; u < kMaxTiles; ++u) {
       v.view_host[u] = nullptr;
       v.view_dev[u] = nullptr;
@@ -480,9 +493,11 @@ void fill_info(pasd_ctx* ctx, pasd_info* info) {
   if (ctx->cfg.precision == PASD_FP64) {
     info->merged_modes = ctx->pd.mfull ? ctx->N : ctx->pd.mmerge;
     info->fused_blocks = ctx->pd.fused_blocks;
+    info->gemm_p_pair = ctx->pd.gp2 ? 1 : 0;
   } else {
     info->merged_modes = ctx->pf.mfull ? ctx->N : ctx->pf.mmerge;
     info->fused_blocks = ctx->pf.fused_blocks;
+    info->gemm_p_pair = ctx->pf.gp2 ? 1 : 0;
   }
 }
 

@@ -74,6 +74,7 @@ class Info(ctypes.Structure):
         ("tol_effective", ctypes.c_double),
         ("merged_modes", ctypes.c_int),
         ("fused_blocks", ctypes.c_int),
+        ("gemm_p_pair", ctypes.c_int),
     ]
 
 

@@ -98,6 +98,10 @@ SHAPES = [
     # memory, and the eigensolver reading U_n from global memory
     ((1000, 12, 10), (10, 4, 4), 0.01, 25),
     ((2100, 8, 6), (16, 4, 3), 0.01, 12),
+    # last two modes 64 x 64: their GEMM-P as one pass over the slabs, with a
+    # partial last block (5 slabs, blocks of 4) and R_N = 16
+    ((5, 64, 64), (3, 5, 7), 0.01, 25),
+    ((2, 3, 64, 64), (2, 3, 11, 16), 0.01, 15),
 ]
 
 
@@ -112,6 +116,9 @@ def test_shapes(dims, ranks, mu0, iters, precision):
     pasd_iterate(st, iters)
     s = _gpu(T, ranks, precision, mu0=mu0)
     s.step(iters)
+    # the last two modes' GEMM-P as one pass exactly where the plan says
+    pair = len(dims) >= 3 and dims[-1] == dims[-2] == 64 and max(ranks) <= 16
+    assert s.query().gemm_p_pair == int(pair)
     _compare(st, s, precision, f"{dims}/{ranks}/{precision}")
 
 
@@ -277,6 +284,7 @@ def test_merged_batch_equals_alone():
         alone.append(a)
         mixed.append(_gpu(T, ranks, "fp64", mu0=0.01))
     assert [m.query().merged_modes for m in mixed] == [4, 4, 2, 0]
+    assert [m.query().gemm_p_pair for m in mixed] == [0, 0, 1, 0]
     for _ in range(3):
         P.step_batch(mixed, 7)
     P.step_batch(mixed, 2)
