@@ -435,3 +435,25 @@ def test_tall_mode_rank_deficient_m_fp64():
           f"rank={list(info.rank[:3])} RSE={rse:.2e}", flush=True)
     assert info.converged == 1 and list(info.rank[:3]) == [3, 3, 3]
     assert rse <= 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,ranks", [((3, 64, 64), (3, 5, 7)), ((2, 3, 64, 64), (2, 3, 6, 16))])
+def test_gemm_p_pair_places_every_entry(dims, ranks, precision):
+    """First iteration (U_n = the leading columns of the identity, Y_n = 0,
+    D = T): every entry of P_n = U_n^T G_n is one product 1 * t plus exact
+    zeros, so P_n must equal the leading R_n rows of each unfolding bitwise,
+    also for the last two modes, which GEMM-P takes in one pass over their
+    64 x 64 slabs."""
+    dt = np.float64 if precision == "fp64" else np.float32
+    T = (np.random.default_rng(77).standard_normal(dims) * 3.0).astype(dt)
+    with P.Solver(T, ranks, precision=precision, tol=0.0, max_iter=1000) as s:
+        s.step(1)
+        assert s.query().gemm_p_pair == 1
+        for n, R in enumerate(ranks):
+            A = int(np.prod(dims[:n]))
+            B = int(np.prod(dims[n + 1:]))
+            want = T.reshape(A, dims[n], B).transpose(1, 0, 2).reshape(dims[n], A * B)[:R]
+            got = s.export(P.Q_P, n)
+            assert got.dtype == dt and got.shape == want.shape, n
+            assert np.array_equal(got, want), n
