@@ -281,7 +281,8 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
 
   if (g.B > 1) {
     __shared__ S red[4][64][16];
-    // B_n a multiple of 256: the four waves take 64 columns each, every row
+    // B_n a multiple of 256 (every 256-column tile full, inside one row run):
+    // wave w takes columns 64 w .. 64 w + 63 of the tile over the whole contraction
     const bool side = (g.B % 256) == 0;
     const int64_t j4 = side ? tile * 256 + wave * 64 + 4 * p : tile * 64 + 4 * p;
     int64_t off[4];
@@ -345,6 +346,7 @@ __global__ void __launch_bounds__(256) k_gemm_p(Batch<S> bt) {
       }
     }
     if (side) {
+      // the wave's own 64 columns are complete: no sum across waves
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = MM<S>::row(q, v);
