@@ -110,3 +110,35 @@ def test_create_rejects_bad_arguments_without_gpu():
     assert rc == binding.ERR_INVALID_ARG and not h.value
     pasd.lib().pasd_destroy(None)  # NULL-safe
 
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of pasd_config and pasd_info have the C layout: a
+    host program compiled from include/pasd.h prints every field's offset and
+    the struct sizes, which must equal what ctypes computes."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"pasd_config": binding.Config, "pasd_info": binding.Info}
+    fields = {name: [f[0] for f in cls._fields_] for name, cls in structs.items()}
+    c_name = {"lambda_": "lambda"}  # a Python keyword in the binding
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pasd.h"', "int main(void) {"]
+    for name, fl in fields.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f in fl:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {c_name.get(f, f)}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    assert len(got) == sum(len(v) for v in fields.values()) + len(structs)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f in fields[name]:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
