@@ -148,7 +148,7 @@ __device__ __forceinline__ void load_g4(const S* __restrict__ D, const S* __rest
 // When 256 divides B_n, a block takes 256 columns instead, wave w the 64
 // from j0 + 64 w, each wave the whole contraction (no sum across waves): every
 // row is then read in 2 KB (FP64) runs rather than 512-byte ones (64^4,
-// modes 0 and 1: 119.6 -> 113 us FP64, FP32 and split-BF16 9 and 13 us less).
+// modes 0 and 1: 119.6 -> 110.5 us FP64, FP32 and split-BF16 9 and 13 us less).
 // Row scheme (B == 1, the last mode): one wave = 16 rows a, lane (p, q) reads
 // G[a0+p][i0+4q .. +3]; A[a][k] = G, B[k][r] = U, all four t accumulate into
 // one tile since they share the output.
