@@ -102,3 +102,15 @@ def test_serving_trace_recipe():
         assert 0.05 <= t["frac"] <= 0.20
     # seeded: the same trace twice
     assert workloads.serving_trace(count=8, qps=100.0) == trace[:8]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark measures one GPU; asking for more ends at once with a
+    # message and exit status 2, before anything touches a device
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--gpus 2 is not supported" in r.stderr
+    assert r.stdout == ""
