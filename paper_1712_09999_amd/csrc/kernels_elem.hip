@@ -101,14 +101,18 @@ __device__ __forceinline__ void gload(const S* base, IT idx, S out[VEC]) {
   }
 }
 
+// nt: non-temporal store (Problem::ntstore)
 template <typename S, int VEC, typename IT>
-__device__ __forceinline__ void gstore(S* base, IT idx, const S in[VEC]) {
+__device__ __forceinline__ void gstore(S* base, IT idx, const S in[VEC], bool nt) {
   PASD_GLOBAL char* p = (PASD_GLOBAL char*)base + byte_off<S, IT>(idx);
   if constexpr (VEC > 1) {
     typename VW<S>::t v;
 #pragma unroll
     for (int t = 0; t < VEC; ++t) v[t] = in[t];
-    *(PASD_GLOBAL typename VW<S>::t*)p = v;
+    if (nt)
+      __builtin_nontemporal_store(v, (PASD_GLOBAL typename VW<S>::t*)p);
+    else
+      *(PASD_GLOBAL typename VW<S>::t*)p = v;
   } else {
     *(PASD_GLOBAL S*)p = in[0];
   }
@@ -162,6 +166,7 @@ struct FusedView {
   int NT[NN];      // rank tiles (the tile-looped rank path)
   IT IN, Q, nchunk;
   FastDiv fq, frb[NN], fi[NN];
+  int nt;  // Problem::ntstore
 };
 
 template <typename S, int NN, int VEC, typename IT>
@@ -173,6 +178,7 @@ __device__ __forceinline__ FusedView<S, NN, IT> fused_view(const Problem<S>& pb)
   v.Q = v.IN / VEC;
   v.nchunk = (IT)(pb.numel / VEC);
   v.fq = pb.fd_q;
+  v.nt = pb.ntstore;
 #pragma unroll
   for (int n = 0; n < NN; ++n) {
     v.Y[n] = pb.m[n].Y;
@@ -803,9 +809,9 @@ __device__ __forceinline__ void fused_body(const Problem<S>& pb, int lblk, int n
       }
       rmax[NN].add(d);
     }
-    gstore<S, VEC, IT>(v.D, x0, dv);
+    gstore<S, VEC, IT>(v.D, x0, dv, v.nt != 0);
 #pragma unroll
-    for (int n = 0; n < NN; ++n) gstore<S, VEC, IT>(v.Y[n], x0, y[n]);
+    for (int n = 0; n < NN; ++n) gstore<S, VEC, IT>(v.Y[n], x0, y[n], v.nt != 0);
     if constexpr (MM > 0) {
 #pragma unroll
       for (int n = 0; n < MM; ++n) macc_add<S, VEC, RP>(macc[n], pk[n], dv, y[n], inv_mu_next);

@@ -154,6 +154,13 @@ struct Problem {
   // R_n <= kRT, I_{N-2} = I_{N-1} = 64, N >= 3): one per 64 x 64 slab, 0
   // otherwise; those modes then have no blocks of their own in kb[KB_GEMM_P]
   int gp2;
+  // The fused pass writes D and Y_n with non-temporal stores: together they
+  // exceed the 256 MB Infinity Cache ((N + 1) L s > 256 MiB), so no later
+  // kernel finds them there, and allocating them in the caches only evicts the
+  // factor columns the pass re-reads (64^4 FP64: 0.588 -> 0.584 ms per
+  // iteration; at 200^3 FP32, 128 MB, GEMM-M rereads them from the Infinity
+  // Cache and non-temporal stores cost it 5 us).
+  int ntstore;
   // fused pass divisors: chunks per row of the last mode, and per mode n < N-1
   // the rows per mode-n fibre index (B_n / I_N) and I_n
   FastDiv fd_q;

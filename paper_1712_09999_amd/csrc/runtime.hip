@@ -273,6 +273,7 @@ void fill_problem(pasd_ctx* ctx, const Plan& pl, Problem<S>& p) {
   p.idx32 = pl.idx32;
   p.mmerge = pl.mmerge;
   p.mfull = pl.mfull;
+  p.ntstore = (int64_t)(ctx->N + 1) * ctx->numel * (int64_t)sizeof(S) > (int64_t(256) << 20) ? 1 : 0;
   p.mcb = (uint32_t)pl.mcb;
   for (int n = 0; n < kMaxN; ++n)
     p.mslab[n] = n < pl.mmerge ? (int)(p.g[n].B / pl.vec / pl.mcb) : 0;
